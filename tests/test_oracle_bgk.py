@@ -1,0 +1,204 @@
+"""Pins of the FP64 BGK oracle against closed forms, invariants and a
+textbook eigenvalue computation (no GPU).
+
+Paper: Methodology, "Lattice Boltzmann Method" (Eq. 1 update, Eq. 2
+equilibrium); validation section "Taylor-Green Vortex Validation".
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_14494_amd import inputs
+
+
+def test_lattice_isotropy(orc):
+    ex, ey, w = orc.lattice()
+    cs2 = 1.0 / 3.0
+    e = np.stack([ex, ey], 1).astype(float)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs((w[:, None] * e).sum(0)).max() < 1e-15
+    second = np.einsum("i,ia,ib->ab", w, e, e)
+    assert np.abs(second - cs2 * np.eye(2)).max() < 1e-15
+    fourth = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    d = np.eye(2)
+    iso = cs2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                      + np.einsum("ad,bc->abcd", d, d))
+    assert np.abs(fourth - iso).max() < 1e-15
+    # opposite pairs and |e|^2 classes of D2Q9
+    for i in range(9):
+        j = [k for k in range(9) if ex[k] == -ex[i] and ey[k] == -ey[i]]
+        assert len(j) == 1 and w[j[0]] == w[i]
+
+
+@pytest.mark.parametrize("rho,ux,uy", [(1.0, 0.0, 0.0), (1.03, 0.05, -0.02),
+                                       (0.97, -0.1, 0.07)])
+def test_equilibrium_moments(orc, rho, ux, uy):
+    ex, ey, _ = orc.lattice()
+    feq = orc.equilibrium(rho, ux, uy)
+    assert abs(feq.sum() - rho) < 1e-15
+    assert abs((ex * feq).sum() - rho * ux) < 1e-15
+    assert abs((ey * feq).sum() - rho * uy) < 1e-15
+    u = np.array([ux, uy])
+    e = np.stack([ex, ey], 1)
+    pi = np.einsum("i,ia,ib->ab", feq, e, e)
+    expect = rho / 3.0 * np.eye(2) + rho * np.outer(u, u)
+    assert np.abs(pi - expect).max() < 1e-15
+
+
+def test_equilibrium_fixed_point_and_local_conservation(orc):
+    rng = np.random.default_rng(1)
+    ny, nx = 5, 7
+    rho = 1 + 0.05 * rng.standard_normal((ny, nx))
+    ux = 0.05 * rng.standard_normal((ny, nx))
+    uy = 0.05 * rng.standard_normal((ny, nx))
+    feq = orc.init_equilibrium(rho, ux, uy)
+    assert np.abs(orc.collide_bgk(feq, 0.8) - feq).max() < 1e-15
+    _, _, w = orc.lattice()
+    f = w[:, None, None] * (1 + 0.1 * rng.standard_normal((9, ny, nx)))
+    fs = orc.collide_bgk(f, 0.6)
+    ex, ey, _ = orc.lattice()
+    for a, b in ((f, fs),):
+        assert np.abs(a.sum(0) - b.sum(0)).max() < 1e-15
+        assert np.abs((ex[:, None, None] * (a - b)).sum(0)).max() < 1e-15
+        assert np.abs((ey[:, None, None] * (a - b)).sum(0)).max() < 1e-15
+    # BGK relaxes f^neq by exactly (1 - 1/tau)
+    r2, ux2, uy2 = orc.moments(f)
+    feq2 = orc.init_equilibrium(r2, ux2, uy2)
+    assert np.abs((fs - feq2) - (1 - 1 / 0.6) * (f - feq2)).max() < 1e-15
+
+
+def test_streaming_is_a_permutation(orc):
+    rng = np.random.default_rng(2)
+    ny, nx = 4, 6
+    f = rng.standard_normal((9, ny, nx))
+    g = f.copy()
+    for _ in range(math.lcm(nx, ny)):
+        g = orc.stream(g)
+    assert np.array_equal(g, f)
+    assert np.array_equal(orc.unstream(orc.stream(f)), f)
+    # direction 1 = (+1, 0) moves one cell in +x
+    s = orc.stream(f)
+    assert np.array_equal(s[1], np.roll(f[1], 1, axis=1))
+    assert np.array_equal(s[2], np.roll(f[2], 1, axis=0))
+    assert np.array_equal(s[7], np.roll(np.roll(f[7], -1, axis=1), -1, axis=0))
+
+
+def test_uniform_flow_is_steady(orc):
+    ny, nx = 8, 8
+    rho = np.ones((ny, nx))
+    ux = np.full((ny, nx), 0.05)
+    uy = np.full((ny, nx), -0.03)
+    f = orc.init_equilibrium(rho, ux, uy)
+    g = orc.bgk_run(f, 0.7, 1000)
+    assert np.abs(g - f).max() < 1e-14
+
+
+def test_global_conservation(orc):
+    rng = np.random.default_rng(3)
+    ny, nx = 12, 16
+    _, _, w = orc.lattice()
+    f = w[:, None, None] * (1 + 0.05 * rng.standard_normal((9, ny, nx)))
+    s0 = orc.observables(f)
+    g = orc.bgk_run(f, 0.62, 1000)
+    s1 = orc.observables(g)
+    assert abs(s1[0] - s0[0]) / s0[0] < 1e-12
+    assert abs(s1[1] - s0[1]) < 1e-12 * s0[0]
+    assert abs(s1[2] - s0[2]) < 1e-12 * s0[0]
+
+
+def _shear_eigenvalue(orc, q, omega):
+    """Eigenvalue of the linearised one-step operator L(q) = S(q)[I - w(I - E)]
+    whose eigenvector overlaps most with a transverse velocity perturbation."""
+    ex, ey, w = orc.lattice()
+    e = np.stack([ex, ey], 1).astype(float)
+    E = w[:, None] * (1 + 3 * e @ e.T)
+    S = np.diag(np.exp(-1j * (e @ q)))
+    L = S @ (np.eye(9) - omega * (np.eye(9) - E))
+    vals, vecs = np.linalg.eig(L)
+    t = np.array([-q[1], q[0]]) / np.linalg.norm(q)
+    probe = w * 3 * (e @ t)
+    k = np.argmax(np.abs(vecs.conj().T @ probe) / np.linalg.norm(vecs, axis=0))
+    return vals[k]
+
+
+def test_tiny_tgv_decays_at_linear_shear_eigenvalue(orc):
+    n, tau, u0 = 32, 0.62, 1e-5
+    k = 2 * np.pi / n
+    lam = _shear_eigenvalue(orc, np.array([k, k]), 1 / tau)
+    assert abs(lam.imag) < 1e-12
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0)
+    f = orc.init_equilibrium(rho, ux, uy)
+    mode = ux / u0
+
+    def amp(f):
+        _, u, _ = orc.moments(f)
+        return (u * mode).sum()
+
+    f = orc.bgk_run(f, tau, 300)
+    a0 = amp(f)
+    f = orc.bgk_run(f, tau, 100)
+    a1 = amp(f)
+    rate = (a1 / a0) ** (1 / 100)
+    assert abs(rate - lam.real) / lam.real < 1e-9
+    # hydrodynamic limit: lambda ~ exp(-nu |q|^2), nu = c_s^2 (tau - 1/2)
+    nu = (tau - 0.5) / 3
+    assert abs(np.log(lam.real) + nu * 2 * k * k) / (nu * 2 * k * k) < 0.02
+
+
+def test_tgv_64_re100_against_analytic_decay(orc):
+    n, u0 = 64, 0.04
+    nu, tau = inputs.tgv_params(n, u0, 100.0)
+    assert abs(tau - 0.5768) < 1e-12
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0)
+    f = orc.init_equilibrium(rho, ux, uy)
+    energies = []
+    for s in range(10):
+        f = orc.bgk_run(f, tau, 100)
+        energies.append(orc.observables(f)[3])
+    spec = inputs.tgv_spec(n, n, u0, nu, 1000)
+    obs = orc.observables(f, spec)
+    eps_u = math.sqrt(obs[4] / obs[5])
+    # uniform-density start: the acoustic transient sets this floor
+    assert eps_u < 5e-3
+    # energy decays as exp(-4 nu k^2 t) with k^2 per axis: fit over 500..1000
+    k2 = (2 * np.pi / n) ** 2
+    slope = np.polyfit(np.arange(500, 1001, 100), np.log(energies[4:]), 1)[0]
+    nu_fit = -slope / (4 * k2)
+    assert abs(nu_fit - nu) / nu < 0.01
+
+
+def test_restriction_of_equilibrium_is_coarse_equilibrium(orc):
+    nf, factor, u0 = 32, 4, 0.05
+    rho, ux, uy = inputs.tgv_velocity(nf, nf, u0, x0=3.3, y0=-1.7)
+    ff = orc.init_equilibrium(rho, ux, uy)
+    fc = orc.restrict(ff, factor, 0.56, 0.51)
+    nc = nf // factor
+    rc, uxc, uyc = inputs.tgv_velocity(nc, nc, u0, x0=3.3 / factor, y0=-1.7 / factor)
+    expect = orc.init_equilibrium(rc, uxc, uyc)
+    assert np.abs(fc - expect).max() < 1e-15
+    back = orc.stream(orc.restrict(ff, factor, 0.56, 0.51, unstream_=True))
+    assert np.abs(back - fc).max() == 0.0
+
+
+def test_restriction_rescales_nonequilibrium_part(orc):
+    rng = np.random.default_rng(5)
+    nf, factor = 16, 4
+    _, _, w = orc.lattice()
+    ff = w[:, None, None] * (1 + 0.02 * rng.standard_normal((9, nf, nf)))
+    tf, tc = 0.55, 0.52
+    fc = orc.restrict(ff, factor, tf, tc)
+    ex, ey, _ = orc.lattice()
+    e = np.stack([ex, ey], 1)
+    sub = ff[:, ::factor, ::factor]
+    r_f, ux_f, uy_f = orc.moments(sub)
+    r_c, ux_c, uy_c = orc.moments(fc)
+    assert np.abs(r_f - r_c).max() < 1e-14
+    assert np.abs(ux_f - ux_c).max() < 1e-14
+    assert np.abs(uy_f - uy_c).max() < 1e-14
+    neq_f = sub - orc.init_equilibrium(r_f, ux_f, uy_f)
+    neq_c = fc - orc.init_equilibrium(r_c, ux_c, uy_c)
+    lam = factor * tc / tf
+    pi_f = np.einsum("iyx,ia,ib->yxab", neq_f, e, e)
+    pi_c = np.einsum("iyx,ia,ib->yxab", neq_c, e, e)
+    assert np.abs(pi_c - lam * pi_f).max() < 1e-14

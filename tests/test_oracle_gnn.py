@@ -1,0 +1,334 @@
+"""Pins of the GNN-collision oracle (no GPU).
+
+Paper: Methodology, "Graph Neural Network Enhancement" (feature extraction,
+message passing, prediction head), "Integration of GNN with LBM" (Eq. 3),
+"GNN Architecture Details" (tau_adj from a sigmoid scaled to [0.5, 1.5]),
+"Training Methodology" (Eq. 4).  Network sizes follow the 12 -> 64 -> 64,
+two-round, 64 -> 10 workload definition.
+"""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from paper_2504_14494_amd import inputs
+
+R = 2
+
+
+def _state(orc, shape, seed, amp=0.004):
+    _, _, w = orc.lattice()
+    g = inputs.random_shifted_state(shape, amp, seed).astype(np.float64)
+    wb = w.reshape((9, 1, 1)) if len(shape) == 3 else w.reshape((1, 9, 1, 1))
+    return g + wb
+
+
+def _blob(seed=0, s_delta=1.0, rounds=R):
+    return inputs.gnn_blob(seed, rounds, s_delta=s_delta).astype(np.float64)
+
+
+def _set(blob, name, value, rounds=R):
+    off, shape = inputs.blob_offsets(rounds)[name]
+    blob[off:off + int(np.prod(shape))] = np.broadcast_to(value, shape).ravel()
+
+
+def test_bf16_rounding_matches_library(orc):
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.standard_normal(2000).astype(np.float32),
+                         np.float32([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -8,
+                                     3.0e-5, -7.77e3])])
+    ref = torch.from_numpy(xs).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([orc.bf16_round(float(x)) for x in xs])
+    assert np.array_equal(got, ref)
+    assert orc.bf16_round(1 + 2 ** -8) == 1.0          # tie to even
+    assert orc.bf16_round(1 + 3 * 2 ** -8) == 1 + 2 ** -6
+
+
+def test_gelu_tanh_form(orc):
+    xs = np.linspace(-8, 8, 161)
+    ref = F.gelu(torch.from_numpy(xs), approximate="tanh").numpy()
+    got = np.array([orc.gelu(x) for x in xs])
+    assert np.abs(got - ref).max() < 1e-15
+    assert abs(orc.gelu(1.0) - 0.8411919906082768) < 1e-15
+    h = 1e-6
+    fd = np.array([(orc.gelu(x + h) - orc.gelu(x - h)) / (2 * h) for x in xs])
+    gg = np.array([orc.gelu_grad(x) for x in xs])
+    assert np.abs(fd - gg).max() < 1e-8
+
+
+def test_projector(orc):
+    ex, ey, _ = orc.lattice()
+    rng = np.random.default_rng(1)
+    M = np.stack([np.ones(9), ex, ey])
+    for _ in range(5):
+        v = rng.standard_normal(9)
+        p = orc.project(v)
+        assert np.abs(M @ p).max() < 1e-15
+        assert np.abs(orc.project(p) - p).max() < 1e-15
+        # closed form, since M M^T = diag(9, 6, 6)
+        cf = v - (v.sum() / 9 + ex * (ex @ v) / 6 + ey * (ey @ v) / 6)
+        assert np.abs(p - cf).max() < 1e-15
+        u = rng.standard_normal(9)
+        assert abs(orc.project(u) @ v - u @ p) < 1e-14   # symmetric
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_zero_head_is_bgk(orc, mode):
+    f = _state(orc, (9, 6, 7), 3)
+    blob = _blob(1)
+    _set(blob, "Wh", 0.0)
+    _set(blob, "bh", 0.0)
+    out = orc.gnn_collide(f, 0.7, blob, mode=mode)
+    assert np.abs(out - orc.collide_bgk(f, 0.7)).max() < 1e-16
+
+
+def test_tau_adjustment_head(orc):
+    f = _state(orc, (9, 5, 5), 4)
+    blob = _blob(2)
+    beta = 0.8
+    _set(blob, "Wh", 0.0)
+    bh = np.zeros(10)
+    bh[0] = beta
+    _set(blob, "bh", bh)
+    out = orc.gnn_collide(f, 0.6, blob)
+    tau_eff = 0.6 * (0.5 + 1 / (1 + np.exp(-beta)))
+    assert np.abs(out - orc.collide_bgk(f, tau_eff)).max() < 1e-16
+
+
+def test_population_correction_head(orc):
+    ex, ey, _ = orc.lattice()
+    f = _state(orc, (9, 4, 6), 5)
+    blob = _blob(3, s_delta=0.01)
+    v = np.linspace(-1, 1, 9)
+    _set(blob, "Wh", 0.0)
+    _set(blob, "bh", np.concatenate([[0.0], v]))
+    out = orc.gnn_collide(f, 0.9, blob)
+    pv = v - (v.sum() / 9 + ex * (ex @ v) / 6 + ey * (ey @ v) / 6)
+    sd = blob[inputs.blob_offsets(R)["s_delta"][0]]
+    expect = orc.collide_bgk(f, 0.9) + sd * pv[:, None, None]
+    assert np.abs(out - expect).max() < 1e-16
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_node_conservation(orc, mode):
+    ex, ey, _ = orc.lattice()
+    f = _state(orc, (9, 6, 6), 6)
+    out = orc.gnn_collide(f, 0.55, _blob(4, s_delta=1e-2), mode=mode)
+    assert np.abs(out.sum(0) - f.sum(0)).max() < 1e-15
+    assert np.abs(np.tensordot(ex, out - f, 1)).max() < 1e-15
+    assert np.abs(np.tensordot(ey, out - f, 1)).max() < 1e-15
+
+
+def test_receptive_field_is_chebyshev_ball(orc):
+    ny, nx = 11, 12
+    f = _state(orc, (9, ny, nx), 7)
+    blob = _blob(5, s_delta=1.0)
+    base = orc.gnn_collide(f, 0.7, blob)
+    f2 = f.copy()
+    sy, sx = 5, 6
+    f2[:, sy, sx] += 1e-3 * np.linspace(-1, 1, 9)
+    diff = np.abs(orc.gnn_collide(f2, 0.7, blob) - base).max(0)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    cheb = np.maximum(np.abs(yy - sy), np.abs(xx - sx))
+    assert np.all(diff[cheb > R] == 0.0)
+    assert np.all(diff[cheb <= R] > 0.0)
+
+
+def test_translation_equivariance(orc):
+    f = _state(orc, (9, 7, 9), 8)
+    blob = _blob(6)
+    out = orc.gnn_collide(f, 0.8, blob)
+    sh = (2, -3)
+    out2 = orc.gnn_collide(np.roll(f, sh, axis=(1, 2)), 0.8, blob)
+    assert np.array_equal(out2, np.roll(out, sh, axis=(1, 2)))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sampled_nodes_match_full_lattice(orc, mode):
+    ny, nx = 9, 10
+    f = _state(orc, (9, ny, nx), 9)
+    blob = _blob(7)
+    full, z = orc.gnn_collide(f, 0.65, blob, mode=mode, want_z=True)
+    nodes = np.array([0, 5, nx - 1, nx * 4 + 3, nx * ny - 1])
+    fs, zs = orc.gnn_collide_nodes(f, 0.65, blob, nodes, mode=mode)
+    assert np.abs(fs - full.reshape(9, -1)[:, nodes].T).max() < 1e-16
+    assert np.abs(zs - z.reshape(-1, 10)[nodes]).max() < 1e-15
+
+
+def test_edge_sender_and_direction(orc):
+    """One round; only channel 0 carries a signal, equal to a known function
+    of each node.  Edge (receiver n, sender n + e_d) with feature e_d must give
+    message GELU(h_sender[0] + a e_dx + b e_dy) on channel 0."""
+    ny, nx = 5, 6
+    rounds = 1
+    f = _state(orc, (9, ny, nx), 10)
+    blob = _blob(8, rounds=rounds)
+    x9 = np.zeros((ny, nx))
+    # encoder: h0[0] = GELU(GELU(x_rho)); all other channels 0
+    W1 = np.zeros((64, 12)); W1[0, 9] = 1.0
+    W2 = np.zeros((64, 64)); W2[0, 0] = 1.0
+    _set(blob, "W1", W1, rounds); _set(blob, "b1", 0.0, rounds)
+    _set(blob, "W2", W2, rounds); _set(blob, "b2", 0.0, rounds)
+    a, b = 0.7, -0.4
+    We = np.zeros((64, 130)); We[0, 64] = 1.0; We[0, 128] = a; We[0, 129] = b
+    _set(blob, "We0", We, rounds); _set(blob, "be0", 0.0, rounds)
+    Wn = np.zeros((64, 128)); Wn[0, 64] = 1.0         # h1[0] = GELU(agg[0])
+    _set(blob, "Wn0", Wn, rounds); _set(blob, "bn0", 0.0, rounds)
+    Wh = np.zeros((10, 64)); Wh[0, 0] = 1.0           # z0 = h1[0]
+    _set(blob, "Wh", Wh, rounds); _set(blob, "bh", 0.0, rounds)
+    off_mu = inputs.blob_offsets(rounds)["mu"][0]
+    mu, sigma = blob[off_mu + 9], blob[off_mu + 12 + 9]
+    rho = f.sum(0)
+    x9 = (rho - 1 - mu) / sigma
+    h0 = np.vectorize(orc.gelu)(np.vectorize(orc.gelu)(x9))
+    ex, ey, _ = orc.lattice()
+    agg = np.zeros((ny, nx))
+    for d in range(1, 9):
+        sender = np.roll(h0, (-ey[d], -ex[d]), axis=(0, 1))   # h0 at n + e_d
+        agg += np.vectorize(orc.gelu)(sender + a * ex[d] + b * ey[d])
+    expect_z0 = np.vectorize(orc.gelu)(agg)
+    _, z = orc.gnn_collide(f, 0.7, blob, rounds=rounds, want_z=True)
+    assert np.abs(z[..., 0] - expect_z0).max() < 1e-14
+
+
+# ------------------------------------------------------------- gradients ---
+
+def _loss_and_grad(orc, f, G, tau, blob, mode=0):
+    out = orc.gnn_collide(f, tau, blob, mode=mode)
+    return float((G * out).sum()), orc.gnn_backward(f, G, tau, blob, mode=mode)
+
+
+def test_backward_matches_central_differences(orc):
+    B, ny, nx = 2, 5, 6
+    f = _state(orc, (B, 9, ny, nx), 11)
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal(f.shape)
+    tau = np.array([0.6, 0.9])
+    blob = _blob(10, s_delta=0.3)
+    _, grad = _loss_and_grad(orc, f, G, tau, blob)
+    npar = orc.param_count(R)
+    offs = inputs.blob_offsets(R)
+    eps = 1e-5
+    for name, _, _ in inputs.gnn_tensor_shapes(R):
+        off, shape = offs[name]
+        n = int(np.prod(shape))
+        v = np.zeros(npar)
+        v[off:off + n] = rng.standard_normal(n)
+        bp, bm = blob.copy(), blob.copy()
+        bp[:npar] += eps * v
+        bm[:npar] -= eps * v
+        lp = float((G * orc.gnn_collide(f, tau, bp)).sum())
+        lm = float((G * orc.gnn_collide(f, tau, bm)).sum())
+        fd = (lp - lm) / (2 * eps)
+        an = float(grad @ v)
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), name
+
+
+def _torch_net(f, tau, blob, rounds=R):
+    """The same network written with torch CPU ops (float64), used as a third,
+    independently written checker of the oracle forward and backward."""
+    offs = inputs.blob_offsets(rounds)
+    P = {k: blob[o:o + int(np.prod(s))].view(*s) for k, (o, s) in offs.items()}
+    ex = torch.tensor([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=torch.float64)
+    ey = torch.tensor([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=torch.float64)
+    w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64)
+    rho = f.sum(1)
+    ux = (f * ex[None, :, None, None]).sum(1) / rho
+    uy = (f * ey[None, :, None, None]).sum(1) / rho
+    feat = torch.cat([f - w[None, :, None, None], (rho - 1)[:, None],
+                      ux[:, None], uy[:, None]], 1).permute(0, 2, 3, 1)
+    x = (feat - P["mu"]) / P["sigma"]
+    g = lambda t: F.gelu(t, approximate="tanh")
+    h = g(F.linear(g(F.linear(x, P["W1"], P["b1"])), P["W2"], P["b2"]))
+    for r in range(rounds):
+        agg = 0
+        for d in range(1, 9):
+            hj = torch.roll(h, (-int(ey[d]), -int(ex[d])), dims=(1, 2))
+            e = torch.tensor([float(ex[d]), float(ey[d])], dtype=torch.float64)
+            inp = torch.cat([h, hj, e.expand(*h.shape[:3], 2)], -1)
+            agg = agg + g(F.linear(inp, P[f"We{r}"], P[f"be{r}"]))
+        h = g(F.linear(torch.cat([h, agg], -1), P[f"Wn{r}"], P[f"bn{r}"]))
+    z = F.linear(h, P["Wh"], P["bh"])
+    tau_adj = 0.5 + torch.sigmoid(z[..., 0])
+    d = z[..., 1:]
+    d = d - (d.sum(-1, keepdim=True) / 9 + ex * (d * ex).sum(-1, keepdim=True) / 6
+             + ey * (d * ey).sum(-1, keepdim=True) / 6)
+    uu = ux ** 2 + uy ** 2
+    eu = ex[None, :, None, None] * ux[:, None] + ey[None, :, None, None] * uy[:, None]
+    feq = rho[:, None] * w[None, :, None, None] * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * uu[:, None])
+    return (f - (f - feq) / (tau[:, None, None, None] * tau_adj[:, None])
+            + P["s_delta"] * d.permute(0, 3, 1, 2))
+
+
+def test_torch_composition_agrees(orc):
+    B, ny, nx = 2, 4, 5
+    f = _state(orc, (B, 9, ny, nx), 13)
+    rng = np.random.default_rng(14)
+    G = rng.standard_normal(f.shape)
+    tau = np.array([0.7, 0.55])
+    blob = _blob(11, s_delta=0.2)
+    bt = torch.tensor(blob, requires_grad=True)
+    out_t = _torch_net(torch.tensor(f), torch.tensor(tau), bt)
+    (out_t * torch.tensor(G)).sum().backward()
+    out = orc.gnn_collide(f, tau, blob)
+    assert np.abs(out - out_t.detach().numpy()).max() < 1e-13
+    grad = orc.gnn_backward(f, G, tau, blob)
+    gt = bt.grad.numpy()[:orc.param_count(R)]
+    assert np.abs(grad - gt).max() <= 1e-10 * np.abs(gt).max()
+
+
+def test_bf16_mode_is_close_to_fp64(orc):
+    f = _state(orc, (9, 8, 8), 15)
+    blob = _blob(12, s_delta=1.0)
+    _, z0 = orc.gnn_collide(f, 0.7, blob, mode=0, want_z=True)
+    _, z1 = orc.gnn_collide(f, 0.7, blob, mode=1, want_z=True)
+    rel = np.linalg.norm(z1 - z0) / np.linalg.norm(z0)
+    assert 1e-4 < rel < 3e-2
+
+
+# -------------------------------------------------- training + fallback ---
+
+def test_mse_is_eq4(orc):
+    rng = np.random.default_rng(16)
+    a = rng.standard_normal((3, 9, 4, 5))
+    b = rng.standard_normal((3, 9, 4, 5))
+    assert abs(orc.mse(a, b) - ((a - b) ** 2).sum() / (3 * 4 * 5)) < 1e-12
+
+
+def test_adam_matches_torch(orc):
+    rng = np.random.default_rng(17)
+    p = rng.standard_normal(50)
+    pt = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m, v = np.zeros(50), np.zeros(50)
+    for step in range(1, 4):
+        g = rng.standard_normal(50)
+        pt.grad = torch.tensor(g)
+        opt.step()
+        orc.adam(p, g, m, v, 1e-3, 0.9, 0.999, 1e-8, step)
+    assert np.abs(p - pt.detach().numpy()).max() < 1e-14
+
+
+def test_fallback_rule(orc):
+    f = _state(orc, (9, 6, 6), 18)
+    tau = 0.7
+    blob = _blob(13, s_delta=1e-4)
+    mass = f.sum()
+    out, flags, m = orc.gnn_collide_gated(f, tau, blob, 1e-6, mass)
+    assert flags == 0
+    assert np.array_equal(out, orc.gnn_collide(f, tau, blob))
+    # a large correction drives populations negative -> plain BGK
+    big = blob.copy()
+    _set(big, "bh", np.concatenate([[0.0], 50.0 * np.linspace(-1, 1, 9)]))
+    big[inputs.blob_offsets(R)["s_delta"][0]] = 1.0
+    out, flags, m = orc.gnn_collide_gated(f, tau, big, 1e-6, mass)
+    assert flags & 1
+    assert np.array_equal(out, orc.collide_bgk(f, tau))
+    assert abs(m - out.sum()) < 1e-12
+    # a negative threshold forces the drift branch
+    out, flags, _ = orc.gnn_collide_gated(f, tau, blob, -1.0, mass)
+    assert flags == 2
+    assert np.array_equal(out, orc.collide_bgk(f, tau))
+    # a wrong previous mass trips the drift test
+    _, flags, _ = orc.gnn_collide_gated(f, tau, blob, 1e-6, mass * (1 + 1e-5))
+    assert flags == 2
