@@ -1,0 +1,215 @@
+/*
+ * lbmgnn.h — C ABI of the MI355X (gfx950) hot path of LBM-GNN
+ * (Li, "LBM-GNN: Graph Neural Network Enhanced Lattice Boltzmann Method",
+ * arXiv 2504.14494): the D2Q9 lattice Boltzmann step with the BGK collision
+ * (Eq. 1, equilibrium Eq. 2) and the GNN-corrected collision (Eq. 3), plus the
+ * hand-written backward pass and optimiser used to train the network (Eq. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller.  The
+ *    library allocates no device memory; scratch space is passed in as
+ *    `workspace` (size from lbm_workspace_bytes) and holds nothing between
+ *    calls.  Host pointers appear only for small structs (lbm_tgv,
+ *    lbm_fallback), which are read during the call.
+ *  - Populations are stored shifted, g_i = f_i - w_i, as structure of arrays
+ *    g[i][y][x] (i = 0..8, x fastest, plane stride nx*ny).  Batched arrays add
+ *    a leading batch index: g[b][i][y][x].  The D2Q9 order is
+ *    i = 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
+ *        7:(-1,-1) 8:(1,-1),  w = 4/9, 1/9 (i = 1..4), 1/36 (i = 5..8).
+ *  - All boundaries are periodic.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is only enqueued; no call synchronises the host.
+ *  - Return value: 0 on success, a negative LBM_E* code on failure; then
+ *    lbm_last_error() (thread-local) describes it.  Argument errors are
+ *    reported before anything is enqueued.
+ *  - Every kernel is deterministic: equal inputs give bitwise equal outputs
+ *    (no floating-point atomics; reductions use a fixed order).
+ *  - Only gfx950 devices are supported (LBM_EUNSUPPORTED otherwise).
+ */
+#ifndef LBMGNN_H
+#define LBMGNN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,       /* bad argument, size or aliasing                 */
+  LBM_EWORKSPACE = -2,   /* workspace / saved buffer too small             */
+  LBM_EDEVICE = -3,      /* HIP runtime or launch error                    */
+  LBM_EUNSUPPORTED = -4  /* current device is not gfx950                   */
+};
+
+/* Thread-local text of the last error ("" if none). */
+const char *lbm_last_error(void);
+
+/* ------------------------------------------------------------------------ *
+ * Lattice Boltzmann, BGK                                                   *
+ * ------------------------------------------------------------------------ */
+
+/* Initial state at equilibrium (Eq. 2): g_i = f_i^eq(rho, u) - w_i at every
+ * node, from caller fields rho, ux, uy [ny][nx].  Since the BGK collision
+ * leaves f^eq unchanged this is also a valid post-collision state, which is
+ * what lbm_step_* consume.  Requires nx, ny >= 1 and nx*ny < 2^31. */
+int lbm_init(float *g, int nx, int ny, const float *rho, const float *ux,
+             const float *uy, void *stream);
+/* Same in FP64 (used to generate training targets on fine lattices). */
+int lbm_init_f64(double *g, int nx, int ny, const double *rho,
+                 const double *ux, const double *uy, void *stream);
+
+/* One time step of Eq. 1 in fused pull form.  g_src holds the post-collision
+ * state of step t-1; the kernel gathers g_i(x) = g_src_i(x - e_i)
+ * (streaming), forms rho and u, relaxes toward f^eq with omega = 1/tau and
+ * writes the post-collision state of step t to g_dst.  g_src and g_dst must
+ * not overlap (A/B buffers).  tau > 0.5 is expected but not enforced. */
+int lbm_step_bgk(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                 void *stream);
+/* Same in FP64. */
+int lbm_step_bgk_f64(const double *g_src, double *g_dst, int nx, int ny,
+                     double tau, void *stream);
+
+/* Analytic decaying Taylor-Green field used for the error sums:
+ * u_x = -u0 cos(kx X) sin(ky Y) D, u_y = u0 (kx/ky) sin(kx X) cos(ky Y) D,
+ * X = x - x0, Y = y - y0, D = exp(-nu (kx^2 + ky^2) t). */
+typedef struct lbm_tgv {
+  double u0, kx, ky, x0, y0, nu, t;
+} lbm_tgv;
+
+/* Macroscopic fields and FP64 observables of a (post-collision) state.
+ * rho, ux, uy: [ny][nx] FP32 outputs, each may be NULL.
+ * sums: NULL or device double[8] receiving
+ *   [0] total mass  sum rho          [1] sum rho u_x    [2] sum rho u_y
+ *   [3] kinetic energy 1/2 sum |u|^2
+ *   [4] sum |u - u_a|^2   [5] sum |u_a|^2   (0 if analytic == NULL)
+ *   [6] smallest population f_i      [7] number of f_i < 0
+ * analytic: host pointer or NULL.  The sums are accumulated in FP64 from
+ * per-node FP64 moments of the FP32 populations, in a fixed order.
+ * workspace: >= lbm_workspace_bytes(LBM_WS_MOMENTS, 1, nx, ny, 0) bytes. */
+int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux,
+                float *uy, const lbm_tgv *analytic, double *sums,
+                void *workspace, size_t ws_bytes, void *stream);
+
+/* Restriction of a fine FP64 run onto a coarse FP32 lattice (training data).
+ * g_fine [9][nyf][nxf] FP64 shifted; if `pull` is set it is read through one
+ * streaming step (a post-collision state becomes the next pre-collision one),
+ * else it is taken as a pre-collision state.  Coarse node X sits on fine node
+ * factor*X; its populations are f^eq(rho, u) of that fine node plus the
+ * fine non-equilibrium momentum flux Pi^neq rebuilt as
+ * w_i/(2 c_s^4) Q_i:Pi^neq scaled by factor*tau_c/tau_f.  If `unstream` is set
+ * the coarse result is taken back through one coarse streaming step
+ * (out_i(X) = R_i(X + e_i)), turning a pre-collision state of coarse step
+ * m+1 into the post-collision state of step m.  nxf, nyf must be multiples of
+ * factor.  Output g_coarse [9][nyf/factor][nxf/factor] FP32 shifted. */
+int lbm_restrict(const double *g_fine, int nxf, int nyf, int factor,
+                 double tau_f, double tau_c, int pull, int unstream,
+                 float *g_coarse, void *stream);
+
+/* Plain copy of n floats (bandwidth reference for the BGK kernel). */
+int lbm_copy(const float *src, float *dst, size_t n, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * GNN-corrected collision (Eq. 3)                                          *
+ * ------------------------------------------------------------------------ */
+
+/* Parameter blob (FP32, row-major W[out][in]):
+ *   W1[64][12] b1[64] W2[64][64] b2[64]                     encoder
+ *   { We[64][130] be[64] Wn[64][128] bn[64] } x n_rounds    message passing
+ *   Wh[10][64] bh[10]                                       head
+ *   mu[12] sigma[12] s_delta                                constants
+ * The first gnn_param_count(n_rounds) floats are trainable.  Features per
+ * node are ((g_i)_{0..8}, rho - 1, u_x, u_y), normalised as (x - mu)/sigma.
+ * Edge input is [h_receiver; h_sender; e_d] for the 8 neighbours
+ * sender = receiver + e_d.  Activations are the tanh form of GELU.  The head
+ * gives tau_adj = 0.5 + sigmoid(z_0) and the correction
+ * delta f = s_delta * P z_{1..9}, P the orthogonal projector onto the null
+ * space of the mass and momentum moments.  Weights and stored activations
+ * are BF16 (round to nearest even) with FP32 accumulation; the head output
+ * and the collision are FP32.  1 <= n_rounds <= 4. */
+size_t gnn_param_count(int n_rounds);
+size_t gnn_blob_len(int n_rounds);
+
+/* Per-step fallback to plain BGK.  A step falls back when a post-collision
+ * population is negative or not finite (bit 1) or when the relative change
+ * of total mass against *mass is not <= drift_threshold (bit 2); the step's
+ * output is then recomputed with the plain BGK collision from the same
+ * source.  All pointers are device pointers:
+ *   flags       OR-ed with the bits of this step (sticky; caller clears)
+ *   n_fallback  incremented once per step that fell back (may be NULL)
+ *   mass        FP64 total mass of the previous state; read, then replaced
+ *               by the mass of this step's output.
+ * A negative threshold forces the drift branch (used by tests). */
+typedef struct lbm_fallback {
+  double drift_threshold;
+  unsigned *flags;
+  unsigned *n_fallback;
+  double *mass;
+} lbm_fallback;
+
+/* One time step with the GNN-corrected collision: pull streaming as in
+ * lbm_step_bgk, then features, encoder, n_rounds rounds of message passing,
+ * head, projection and Eq. 3, written to g_dst.  fb: host pointer or NULL
+ * (no fallback gate).  workspace: >= lbm_workspace_bytes(LBM_WS_GNN_STEP,
+ * 1, nx, ny, n_rounds) bytes.  params: device blob of gnn_blob_len floats. */
+int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                 const float *params, int n_rounds, const lbm_fallback *fb,
+                 void *workspace, size_t ws_bytes, void *stream);
+
+/* The GNN-corrected collision alone (no streaming) on a batch of
+ * independent periodic lattices: g_pre [batch][9][ny][nx] pre-collision,
+ * g_post the corrected post-collision state, tau: device float[batch].
+ * head_out: NULL or [batch][ny][nx][10] FP32 head outputs z.
+ * saved: NULL for inference, or >= lbm_workspace_bytes(LBM_WS_GNN_SAVED, ...)
+ * bytes that receive the activations gnn_backward needs.
+ * workspace: >= lbm_workspace_bytes(LBM_WS_GNN_FORWARD, ...) bytes. */
+int gnn_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
+                const float *tau, const float *params, int n_rounds,
+                float *head_out, void *saved, size_t saved_bytes,
+                void *workspace, size_t ws_bytes, void *stream);
+
+/* Gradient of a scalar loss with respect to the trainable parameters, given
+ * dL_dgpost = dL/d g_post at the output of the gnn_forward call that filled
+ * `saved` (same g_pre, tau and params).  BF16 rounding of the forward is
+ * treated as the identity.  grad: device float[gnn_param_count(n_rounds)],
+ * overwritten.  workspace: >= lbm_workspace_bytes(LBM_WS_GNN_BACKWARD, ...). */
+int gnn_backward(const float *dL_dgpost, const float *g_pre, const void *saved,
+                 int batch, int nx, int ny, const float *tau,
+                 const float *params, int n_rounds, float *grad,
+                 void *workspace, size_t ws_bytes, void *stream);
+
+/* Eq. 4 with N = batch*nx*ny nodes: loss = scale/N * sum (a - b)^2 over all
+ * nodes and the 9 populations, accumulated in FP64 into *loss (device
+ * double); grad_a (NULL or like a) receives d loss / d a in FP32.
+ * workspace: >= lbm_workspace_bytes(LBM_WS_MSE, batch, nx, ny, 0) bytes. */
+int gnn_mse(const float *a, const float *b, int batch, int nx, int ny,
+            double scale, double *loss, float *grad_a, void *workspace,
+            size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba) on n FP32 parameters with FP32 moments m, v
+ * (zero before the first step); step is the 1-based count after this one. */
+int gnn_adam(float *params, const float *grad, float *m, float *v, size_t n,
+             float lr, float beta1, float beta2, float eps, int step,
+             void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Workspace sizes                                                          *
+ * ------------------------------------------------------------------------ */
+enum {
+  LBM_WS_MOMENTS = 0,
+  LBM_WS_GNN_STEP = 1,
+  LBM_WS_GNN_FORWARD = 2,
+  LBM_WS_GNN_SAVED = 3,
+  LBM_WS_GNN_BACKWARD = 4,
+  LBM_WS_MSE = 5
+};
+/* Bytes needed by operation `op` for the given sizes (0 if op is unknown). */
+size_t lbm_workspace_bytes(int op, int batch, int nx, int ny, int n_rounds);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMGNN_H */

@@ -1,0 +1,170 @@
+"""Python face of the C ABI: torch tensors in, raw device pointers out.
+
+Functions keep the C names (lbm_init, lbm_step_bgk, ...).  PyTorch supplies
+device memory and the current HIP stream; all arithmetic runs in
+liblbmgnn.so.  Populations are shifted (g = f - w) SoA tensors shaped
+[9, ny, nx] (or [batch, 9, ny, nx]).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import LbmFallback, LbmTgv, check
+
+__all__ = [
+    "lbm_init", "lbm_step_bgk", "lbm_moments", "lbm_restrict", "lbm_copy",
+    "lbm_workspace_bytes", "Workspace", "Lattice",
+]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def _pop_dims(g: torch.Tensor):
+    if g.dim() != 3 or g.shape[0] != 9:
+        raise ValueError(f"populations must be [9, ny, nx], got {tuple(g.shape)}")
+    return int(g.shape[2]), int(g.shape[1])
+
+
+def lbm_workspace_bytes(op: int, batch: int, nx: int, ny: int, n_rounds: int = 0) -> int:
+    return int(_lib.load().lbm_workspace_bytes(op, batch, nx, ny, n_rounds))
+
+
+class Workspace:
+    """Grows-only byte buffer on the current device, reused across calls."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes or not self.buf.is_cuda:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+_ws = Workspace()
+
+
+def lbm_init(g: torch.Tensor, rho: torch.Tensor, ux: torch.Tensor, uy: torch.Tensor):
+    dt = g.dtype
+    for t, n in ((g, "g"), (rho, "rho"), (ux, "ux"), (uy, "uy")):
+        _need(t, dt, n)
+    nx, ny = _pop_dims(g)
+    for t in (rho, ux, uy):
+        if tuple(t.shape) != (ny, nx):
+            raise ValueError("fields must be [ny, nx]")
+    fn = _lib.load().lbm_init if dt == torch.float32 else _lib.load().lbm_init_f64
+    check(fn(_ptr(g), nx, ny, _ptr(rho), _ptr(ux), _ptr(uy), _stream()), "lbm_init")
+    return g
+
+
+def lbm_step_bgk(src: torch.Tensor, dst: torch.Tensor, tau: float):
+    _need(src, src.dtype, "src")
+    _need(dst, src.dtype, "dst")
+    nx, ny = _pop_dims(src)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst shapes differ")
+    if src.dtype == torch.float32:
+        rc = _lib.load().lbm_step_bgk(_ptr(src), _ptr(dst), nx, ny, float(tau), _stream())
+    elif src.dtype == torch.float64:
+        rc = _lib.load().lbm_step_bgk_f64(_ptr(src), _ptr(dst), nx, ny, float(tau), _stream())
+    else:
+        raise TypeError("populations must be float32 or float64")
+    check(rc, "lbm_step_bgk")
+    return dst
+
+
+def lbm_moments(g: torch.Tensor, analytic=None, fields: bool = False, sums: bool = True,
+                ws: Workspace = None):
+    """Returns (rho, ux, uy, sums) — fields are None unless requested; sums is a
+    device float64 tensor [8] (see lbmgnn.h) or None."""
+    _need(g, torch.float32, "g")
+    nx, ny = _pop_dims(g)
+    rho = ux = uy = None
+    if fields:
+        rho, ux, uy = (torch.empty((ny, nx), dtype=torch.float32, device=g.device)
+                       for _ in range(3))
+    out = torch.empty(8, dtype=torch.float64, device=g.device) if sums else None
+    wsb = lbm_workspace_bytes(_lib.LBM_WS_MOMENTS, 1, nx, ny)
+    buf = (ws or _ws).get(wsb)
+    tgv = None
+    if analytic is not None:
+        tgv = ctypes.byref(LbmTgv(*[float(v) for v in analytic]))
+    rc = _lib.load().lbm_moments(_ptr(g), nx, ny, _ptr(rho), _ptr(ux), _ptr(uy), tgv,
+                                 _ptr(out), _ptr(buf), buf.numel(), _stream())
+    check(rc, "lbm_moments")
+    return rho, ux, uy, out
+
+
+def lbm_restrict(g_fine: torch.Tensor, factor: int, tau_f: float, tau_c: float,
+                 pull: bool, unstream: bool, out: torch.Tensor = None):
+    _need(g_fine, torch.float64, "g_fine")
+    nxf, nyf = _pop_dims(g_fine)
+    if out is None:
+        out = torch.empty((9, nyf // factor, nxf // factor), dtype=torch.float32,
+                          device=g_fine.device)
+    _need(out, torch.float32, "out")
+    rc = _lib.load().lbm_restrict(_ptr(g_fine), nxf, nyf, factor, float(tau_f), float(tau_c),
+                                  int(pull), int(unstream), _ptr(out), _stream())
+    check(rc, "lbm_restrict")
+    return out
+
+
+def lbm_copy(src: torch.Tensor, dst: torch.Tensor):
+    _need(src, torch.float32, "src")
+    _need(dst, torch.float32, "dst")
+    check(_lib.load().lbm_copy(_ptr(src), _ptr(dst), src.numel(), _stream()), "lbm_copy")
+    return dst
+
+
+class Lattice:
+    """A/B population buffers of one periodic D2Q9 lattice on the GPU."""
+
+    def __init__(self, nx: int, ny: int, dtype=torch.float32, device="cuda"):
+        self.nx, self.ny = nx, ny
+        self.a = torch.empty((9, ny, nx), dtype=dtype, device=device)
+        self.b = torch.empty_like(self.a)
+        self.steps = 0
+
+    @property
+    def g(self) -> torch.Tensor:
+        return self.a
+
+    def init(self, rho, ux, uy):
+        dt, dev = self.a.dtype, self.a.device
+        lbm_init(self.a, *(torch.as_tensor(t, dtype=dt, device=dev).contiguous()
+                           for t in (rho, ux, uy)))
+        self.steps = 0
+        return self
+
+    def load(self, g):
+        self.a.copy_(torch.as_tensor(g, dtype=self.a.dtype))
+        return self
+
+    def step_bgk(self, tau: float, n: int = 1):
+        for _ in range(n):
+            lbm_step_bgk(self.a, self.b, tau)
+            self.a, self.b = self.b, self.a
+            self.steps += 1
+        return self
+
+    def moments(self, analytic=None, fields=False):
+        return lbm_moments(self.a, analytic, fields)

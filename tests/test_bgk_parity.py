@@ -1,0 +1,160 @@
+"""GPU parity of the fused BGK pull step, the equilibrium initialisation, the
+moments/observables and the fine-to-coarse restriction against the FP64
+oracle (paper: Eq. 1 and Eq. 2; Taylor-Green validation).
+
+Comparison convention: the GPU buffers hold post-collision states (fused pull
+form).  After n GPU steps from an equilibrium start the GPU holds the
+collision of the oracle's pre-collision state f_n; moments are equal on both
+sides because the collision conserves them.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_14494_amd import inputs
+from paper_2504_14494_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _w(orc):
+    return orc.lattice()[2][:, None, None]
+
+
+def _gpu(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _oracle_post(orc, post0, tau, steps):
+    """Oracle post-collision state after `steps` fused steps from post0."""
+    f = orc.stream(post0)
+    for _ in range(steps - 1):
+        f = orc.bgk_step(f, tau)
+    return orc.collide_bgk(f, tau)
+
+
+def test_tgv_64_re100_1000_steps_matches_fp64_oracle(orc):
+    n, u0, steps = 64, 0.04, 1000
+    nu, tau = inputs.tgv_params(n, u0, 100.0)
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
+    lat = lbm.Lattice(n, n).init(rho, ux, uy)
+    lat.step_bgk(np.float32(tau), steps)
+    spec = inputs.tgv_spec(n, n, u0, nu, steps)
+    r_g, ux_g, uy_g, sums = lat.moments(spec, fields=True)
+    torch.cuda.synchronize()
+    f = orc.init_equilibrium(rho, ux, uy)
+    f = orc.bgk_run(f, float(np.float32(tau)), steps)
+    r_o, ux_o, uy_o = orc.moments(f)
+    du = np.sqrt(((ux_g.cpu().numpy() - ux_o) ** 2 + (uy_g.cpu().numpy() - uy_o) ** 2).sum())
+    rel = du / np.sqrt((ux_o ** 2 + uy_o ** 2).sum())
+    print(f"u rel-L2 vs FP64 oracle after {steps} steps: {rel:.3e}")
+    assert rel <= 1e-5
+    assert np.abs(r_g.cpu().numpy() - r_o).max() < 1e-6
+    s = sums.cpu().numpy()
+    o = orc.observables(f, spec)
+    eps_gpu, eps_orc = math.sqrt(s[4] / s[5]), math.sqrt(o[4] / o[5])
+    # |eps_gpu - eps_orc| <= |u_gpu - u_orc| / |u_a| (triangle inequality)
+    assert abs(eps_gpu - eps_orc) <= 1.01 * rel * math.sqrt(o[5] / (ux_o ** 2 + uy_o ** 2).sum())
+    # mass is summed in FP64; FP32 storage and rounding leave a drift of a few
+    # 1e-9 relative after 1000 steps
+    assert abs(s[0] - o[0]) / o[0] < 1e-7
+    assert abs(s[3] - o[3]) / o[3] <= 2.1 * rel         # kinetic energy ~ |u|^2
+
+
+@pytest.mark.parametrize("ny,nx", [(1, 1), (3, 5), (7, 4), (33, 64), (3, 257), (5, 300),
+                                   (2, 513)])
+def test_small_and_ragged_lattices(orc, ny, nx):
+    post0 = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=nx * 100 + ny)
+    tau, steps = 0.61, 4
+    a = _gpu(post0)
+    b = torch.full_like(a, float("nan"))
+    for _ in range(steps):
+        lbm.lbm_step_bgk(a, b, np.float32(tau))
+        a, b = b, a
+        b.fill_(float("nan"))
+    got = a.cpu().numpy().astype(np.float64)
+    assert np.isfinite(got).all()
+    ref = _oracle_post(orc, post0.astype(np.float64) + _w(orc), float(np.float32(tau)), steps)
+    assert np.abs(got + _w(orc) - ref).max() < 2e-7
+
+
+def test_fp64_step_matches_oracle(orc):
+    ny, nx = 17, 23
+    post0 = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=7).astype(np.float64)
+    a = _gpu(post0, torch.float64)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        lbm.lbm_step_bgk(a, b, 0.7)
+        a, b = b, a
+    ref = _oracle_post(orc, post0 + _w(orc), 0.7, 3)
+    assert np.abs(a.cpu().numpy() + _w(orc) - ref).max() < 5e-15
+
+
+def test_init_matches_oracle_equilibrium(orc):
+    ny, nx = 12, 20
+    rho, ux, uy = inputs.tgv_velocity(nx, ny, 0.05, x0=1.5, dtype=np.float32)
+    rho = rho * np.float32(1.01)
+    g = torch.empty((9, ny, nx), device="cuda")
+    lbm.lbm_init(g, _gpu(rho), _gpu(ux), _gpu(uy))
+    ref = orc.init_equilibrium(rho, ux, uy)
+    assert np.abs(g.cpu().numpy() + _w(orc) - ref).max() < 1e-8
+
+
+def test_moments_and_observables(orc):
+    ny, nx = 40, 24
+    g = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=11)
+    g[3, 5, 7] = -0.5                                   # one negative population
+    spec = inputs.tgv_spec(nx, ny, 0.03, 0.01, 37.0, x0=0.3, y0=-2.0)
+    r, ux, uy, sums = lbm.lbm_moments(_gpu(g), spec, fields=True)
+    f = g.astype(np.float64) + _w(orc)
+    ro, uxo, uyo = orc.moments(f)
+    assert np.abs(r.cpu().numpy() - ro).max() < 1e-6
+    assert np.abs(ux.cpu().numpy() - uxo).max() < 1e-7
+    s, o = sums.cpu().numpy(), orc.observables(f, spec)
+    for k in range(6):
+        assert abs(s[k] - o[k]) <= 1e-12 * max(1.0, abs(o[k])), k
+    assert s[6] == o[6] and s[7] == o[7] == 1
+
+
+def test_aliasing_is_rejected():
+    a = torch.zeros((9, 8, 8), device="cuda")
+    with pytest.raises(lbm._lib.LbmError):
+        lbm.lbm_step_bgk(a, a, 0.7)
+
+
+@pytest.mark.parametrize("pull,unstream", [(0, 0), (1, 0), (1, 1), (0, 1)])
+def test_restriction_matches_oracle(orc, pull, unstream):
+    nf, factor = 32, 4
+    gf = inputs.random_shifted_state((9, nf, nf), 3e-3, seed=21).astype(np.float64)
+    out = lbm.lbm_restrict(_gpu(gf, torch.float64), factor, 0.56, 0.515, pull, unstream)
+    f = gf + _w(orc)
+    if pull:
+        f = orc.stream(f)
+    ref = orc.restrict(f, factor, 0.56, 0.515, unstream_=bool(unstream))
+    assert np.abs(out.cpu().numpy().astype(np.float64) + _w(orc) - ref).max() < 1e-8
+
+
+def test_full_size_8192_sampled_rows(orc):
+    """One step at 8192^2 in the benchmark's launch configuration; 12 whole
+    rows (including both wrap rows) checked against the oracle."""
+    n = 8192
+    tau = np.float32(inputs.tgv_params(n, 0.04, 1000.0)[1])
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    src = (torch.randn((9, n, n), device="cuda", generator=gen) * 4e-3)
+    dst = torch.full_like(src, float("nan"))
+    lbm.lbm_step_bgk(src, dst, tau)
+    assert not torch.isnan(dst).any().item()
+    w = _w(orc)
+    w2 = w[:, :, 0]                                      # (9, 1) for one row
+    errs = {}
+    for y in (0, 1, 7, 1000, 2047, 2048, 4095, 4096, 6001, 8000, 8190, 8191):
+        rows = [(y - 1) % n, y, (y + 1) % n]
+        band = src[:, rows, :].double().cpu().numpy() + w
+        ref = orc.collide_bgk(orc.stream(band), float(tau))[:, 1, :]
+        got = dst[:, y, :].double().cpu().numpy() + w2
+        e = np.abs(got - ref)
+        errs[y] = (float(e.max()), np.unravel_index(int(e.argmax()), e.shape))
+    print("max error per checked row (value, (direction, x)):", errs)
+    assert max(v[0] for v in errs.values()) < 1e-7
