@@ -164,8 +164,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_entry(src),
-            "kernel": ("bgk_pull_kernel<float>" if os.environ.get("LBMGNN_BGK_VARIANT") == "1"
-                       or args.n % 4 else "bgk_pull_vec4_kernel"),
+            "kernel": "bgk_pull_kernel<float>",
             "copy_ceiling_gbs": round(cp["gbs"], 1),
             "frac_of_copy": round(achieved / cp["gbs"], 4)}
     out = {

@@ -12,9 +12,11 @@
  *    `workspace` (size from lbm_workspace_bytes) and holds nothing between
  *    calls.  Host pointers appear only for small structs (lbm_tgv,
  *    lbm_fallback), which are read during the call.
- *  - Populations are stored shifted, g_i = f_i - w_i, as structure of arrays
- *    g[i][y][x] (i = 0..8, x fastest, plane stride nx*ny).  Batched arrays add
- *    a leading batch index: g[b][i][y][x].  The D2Q9 order is
+ *  - Populations are stored shifted, g_i = f_i - w_i, as row-interleaved
+ *    structure of arrays g[y][i][x]: lattice row y holds nine contiguous runs
+ *    of nx values, one per direction i = 0..8 (x fastest; element
+ *    (y*9 + i)*nx + x).  Batched arrays add a leading batch index:
+ *    g[b][y][i][x].  The D2Q9 order is
  *    i = 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
  *        7:(-1,-1) 8:(1,-1),  w = 4/9, 1/9 (i = 1..4), 1/36 (i = 5..8).
  *  - All boundaries are periodic.
@@ -94,7 +96,7 @@ int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux,
                 void *workspace, size_t ws_bytes, void *stream);
 
 /* Restriction of a fine FP64 run onto a coarse FP32 lattice (training data).
- * g_fine [9][nyf][nxf] FP64 shifted; if `pull` is set it is read through one
+ * g_fine [nyf][9][nxf] FP64 shifted; if `pull` is set it is read through one
  * streaming step (a post-collision state becomes the next pre-collision one),
  * else it is taken as a pre-collision state.  Coarse node X sits on fine node
  * factor*X; its populations are f^eq(rho, u) of that fine node plus the
@@ -103,7 +105,7 @@ int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux,
  * the coarse result is taken back through one coarse streaming step
  * (out_i(X) = R_i(X + e_i)), turning a pre-collision state of coarse step
  * m+1 into the post-collision state of step m.  nxf, nyf must be multiples of
- * factor.  Output g_coarse [9][nyf/factor][nxf/factor] FP32 shifted. */
+ * factor.  Output g_coarse [nyf/factor][9][nxf/factor] FP32 shifted. */
 int lbm_restrict(const double *g_fine, int nxf, int nyf, int factor,
                  double tau_f, double tau_c, int pull, int unstream,
                  float *g_coarse, void *stream);
@@ -159,7 +161,7 @@ int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
                  void *workspace, size_t ws_bytes, void *stream);
 
 /* The GNN-corrected collision alone (no streaming) on a batch of
- * independent periodic lattices: g_pre [batch][9][ny][nx] pre-collision,
+ * independent periodic lattices: g_pre [batch][ny][9][nx] pre-collision,
  * g_post the corrected post-collision state, tau: device float[batch].
  * head_out: NULL or [batch][ny][nx][10] FP32 head outputs z.
  * saved: NULL for inference, or >= lbm_workspace_bytes(LBM_WS_GNN_SAVED, ...)

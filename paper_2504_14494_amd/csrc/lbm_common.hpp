@@ -59,6 +59,56 @@ __host__ __device__ __forceinline__ T geq_shifted(int i, T drho, T rho, T u, T v
          rho * (EqCoef<T>::B(i) * eu + EqCoef<T>::C(i) * eu * eu - EqCoef<T>::D(i) * uu);
 }
 
+// Index of population i at node (x, y) of a row-interleaved lattice
+// g[y][i][x] with rows of nx values.
+__host__ __device__ __forceinline__ size_t pidx(int nx, int y, int i, int x) {
+  return ((size_t)y * 9 + i) * (size_t)nx + x;
+}
+
+// Pull gather of one node: g_i(x, y) = src_i(x - cx_i, y - cy_i), periodic.
+// `src` points at row 0 of one lattice of ny rows.
+template <typename T>
+__device__ __forceinline__ void pull9(const T *__restrict__ src, int nx, int ny, int x, int y,
+                                      T (&g)[9]) {
+  int xm = x == 0 ? nx - 1 : x - 1;
+  int xp = x == nx - 1 ? 0 : x + 1;
+  int ym = y == 0 ? ny - 1 : y - 1;
+  int yp = y == ny - 1 ? 0 : y + 1;
+  const T *r0 = src + (size_t)y * 9 * nx, *rm = src + (size_t)ym * 9 * nx,
+          *rp = src + (size_t)yp * 9 * nx;
+  g[0] = r0[x];
+  g[1] = r0[(size_t)1 * nx + xm];
+  g[2] = rm[(size_t)2 * nx + x];
+  g[3] = r0[(size_t)3 * nx + xp];
+  g[4] = rp[(size_t)4 * nx + x];
+  g[5] = rm[(size_t)5 * nx + xm];
+  g[6] = rm[(size_t)6 * nx + xp];
+  g[7] = rp[(size_t)7 * nx + xp];
+  g[8] = rp[(size_t)8 * nx + xm];
+}
+
+// Density deviation, density, velocity and |u|^2 of one node from its
+// shifted populations (rho = 1 + sum g, rho u = sum e g).  The summation
+// order pairs opposite directions so that a state at rest sums exactly.
+template <typename T>
+__device__ __forceinline__ void node_moments(const T (&g)[9], T &drho, T &rho, T &u, T &v,
+                                             T &uu) {
+  drho = ((g[0] + (g[1] + g[3])) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
+  T jx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
+  T jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+  rho = T(1) + drho;
+  T inv = T(1) / rho;
+  u = jx * inv;
+  v = jy * inv;
+  uu = u * u + v * v;
+}
+
+// True if the byte ranges [a, a + bytes) and [b, b + bytes) intersect.
+inline bool overlap(const void *a, const void *b, size_t bytes) {
+  const char *p = (const char *)a, *q = (const char *)b;
+  return p < q + bytes && q < p + bytes;
+}
+
 // Host-side error reporting (thread-local message, see lbm_last_error).
 int fail(int code, const char *fmt, ...);
 // Checks that the current device is gfx950 (cached per device).

@@ -3,9 +3,14 @@
 // moments with FP64 observables, and the fine-to-coarse restriction used to
 // build training data.
 //
-// Storage: g_i = f_i - w_i, SoA planes g[i][y][x].  Storing the deviation from
-// the rest weights keeps the FP32 roundoff of the density sum at the level of
-// the flow signal instead of the O(1) weights.
+// Storage: g_i = f_i - w_i in row-interleaved structure-of-arrays form,
+// g[y][i][x]: each lattice row holds nine contiguous runs of nx values, one
+// per direction.  Storing the deviation from the rest weights keeps the FP32
+// roundoff of the density sum at the level of the flow signal instead of the
+// O(1) weights.  Keeping the nine directions of a row together means that
+// the eighteen load and store streams of a step all fall inside a window of
+// three rows (27 nx values) instead of nine planes that are whole lattices
+// apart, which keeps HBM pages and channels busy evenly.
 #include <cstdlib>
 
 #include "lbm_common.hpp"
@@ -17,13 +22,13 @@ namespace lbm {
 template <typename T>
 __global__ void init_kernel(T *__restrict__ g, int nx, int ny, const T *__restrict__ rho,
                             const T *__restrict__ ux, const T *__restrict__ uy) {
-  size_t plane = (size_t)nx * ny;
   size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= plane) return;
+  if (n >= (size_t)nx * ny) return;
+  int x = (int)(n % nx), y = (int)(n / nx);
   T r = rho[n], u = ux[n], v = uy[n];
   T uu = u * u + v * v;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i * plane + n] = geq_shifted<T>(i, r - T(1), r, u, v, uu);
+  for (int i = 0; i < 9; ++i) g[pidx(nx, y, i, x)] = geq_shifted<T>(i, r - T(1), r, u, v, uu);
 }
 
 // ------------------------------------------------------------ BGK, fused ---
@@ -32,154 +37,41 @@ __global__ void init_kernel(T *__restrict__ g, int nx, int ny, const T *__restri
 // populations (already streamed) and is overwritten by the post-collision ones.
 template <typename T>
 __device__ __forceinline__ void bgk_collide(T (&g)[9], T omega) {
-  T drho = ((g[0] + (g[1] + g[3])) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
-  T jx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
-  T jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
-  T rho = T(1) + drho;
-  T inv = T(1) / rho;
-  T u = jx * inv, v = jy * inv;
-  T uu = u * u + v * v;
+  T drho, rho, u, v, uu;
+  node_moments(g, drho, rho, u, v, uu);
 #pragma unroll
   for (int i = 0; i < 9; ++i) g[i] = g[i] + omega * (geq_shifted<T>(i, drho, rho, u, v, uu) - g[i]);
 }
 
-// Pull gather: g_i(x, y) = src_i(x - cx_i, y - cy_i) with periodic wrap.
-template <typename T>
-__device__ __forceinline__ void pull9(const T *__restrict__ src, size_t plane, int nx, int x,
-                                      int xm, int xp, size_t r0, size_t rm, size_t rp,
-                                      T (&g)[9]) {
-  g[0] = src[r0 + x];
-  g[1] = src[1 * plane + r0 + xm];
-  g[2] = src[2 * plane + rm + x];
-  g[3] = src[3 * plane + r0 + xp];
-  g[4] = src[4 * plane + rp + x];
-  g[5] = src[5 * plane + rm + xm];
-  g[6] = src[6 * plane + rm + xp];
-  g[7] = src[7 * plane + rp + xp];
-  g[8] = src[8 * plane + rp + xm];
-}
-
 constexpr int kBgkThreads = 256;
 
-// One thread per node; a block covers kBgkThreads consecutive x of one row.
+// One thread per node.  The grid is one-dimensional: block b covers
+// kBgkThreads consecutive x of row b / bx, bx = ceil(nx / kBgkThreads).
+// Consecutive blocks walk along a row, so blocks that share an x range in
+// neighbouring rows (and hence the rows they pull from) are issued bx apart;
+// when bx is a multiple of the 8 XCDs they land on the same XCD and its L2.
 template <typename T>
 __global__ __launch_bounds__(kBgkThreads) void bgk_pull_kernel(const T *__restrict__ src,
                                                                T *__restrict__ dst, int nx,
-                                                               int ny, T omega) {
-  int x = blockIdx.x * kBgkThreads + threadIdx.x;
-  int y = blockIdx.y;
+                                                               int ny, int bx, T omega) {
+  int y = blockIdx.x / bx;
+  int x = (blockIdx.x - y * bx) * kBgkThreads + threadIdx.x;
   if (x >= nx) return;
-  size_t plane = (size_t)nx * ny;
-  int xm = x == 0 ? nx - 1 : x - 1;
-  int xp = x == nx - 1 ? 0 : x + 1;
-  int ym = y == 0 ? ny - 1 : y - 1;
-  int yp = y == ny - 1 ? 0 : y + 1;
-  size_t r0 = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
   T g[9];
-  pull9(src, plane, nx, x, xm, xp, r0, rm, rp, g);
+  pull9(src, nx, ny, x, y, g);
   bgk_collide(g, omega);
+  T *d = dst + (size_t)y * 9 * nx + x;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(g[i], &dst[i * plane + r0 + x]);
-}
-
-// Four consecutive nodes per thread with 16-byte loads and stores (FP32,
-// nx % 4 == 0).  Directions with cx = +1 read the window x0-1..x0+2 and those
-// with cx = -1 read x0+1..x0+4: one dword-aligned 16-byte load each.  The two
-// threads at the ends of a row, whose windows wrap, gather element-wise.
-typedef float vf4 __attribute__((ext_vector_type(4)));
-constexpr int kVecThreads = 256;
-
-__device__ __forceinline__ vf4 ld4(const float *p) {
-  vf4 r;
-  __builtin_memcpy(&r, p, 16);
-  return r;
-}
-
-__device__ __forceinline__ vf4 ld4_wrap(const float *row, int nx, int x) {
-  vf4 r;
-  r.x = row[x < 0 ? x + nx : (x >= nx ? x - nx : x)];
-  ++x;
-  r.y = row[x < 0 ? x + nx : (x >= nx ? x - nx : x)];
-  ++x;
-  r.z = row[x < 0 ? x + nx : (x >= nx ? x - nx : x)];
-  ++x;
-  r.w = row[x < 0 ? x + nx : (x >= nx ? x - nx : x)];
-  return r;
-}
-
-__global__ __launch_bounds__(kVecThreads) void bgk_pull_vec4_kernel(
-    const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, float omega) {
-  int x0 = (blockIdx.x * kVecThreads + threadIdx.x) * 4;
-  int y = blockIdx.y;
-  if (x0 >= nx) return;
-  size_t plane = (size_t)nx * ny;
-  int ym = y == 0 ? ny - 1 : y - 1;
-  int yp = y == ny - 1 ? 0 : y + 1;
-  const float *r0 = src + (size_t)y * nx, *rm = src + (size_t)ym * nx,
-              *rp = src + (size_t)yp * nx;
-  vf4 v[9];
-  v[0] = ld4(r0 + x0);
-  v[2] = ld4(rm + 2 * plane + x0);
-  v[4] = ld4(rp + 4 * plane + x0);
-  if (x0 > 0 && x0 + 4 < nx) {
-    v[1] = ld4(r0 + 1 * plane + x0 - 1);
-    v[5] = ld4(rm + 5 * plane + x0 - 1);
-    v[8] = ld4(rp + 8 * plane + x0 - 1);
-    v[3] = ld4(r0 + 3 * plane + x0 + 1);
-    v[6] = ld4(rm + 6 * plane + x0 + 1);
-    v[7] = ld4(rp + 7 * plane + x0 + 1);
-  } else {
-    v[1] = ld4_wrap(r0 + 1 * plane, nx, x0 - 1);
-    v[5] = ld4_wrap(rm + 5 * plane, nx, x0 - 1);
-    v[8] = ld4_wrap(rp + 8 * plane, nx, x0 - 1);
-    v[3] = ld4_wrap(r0 + 3 * plane, nx, x0 + 1);
-    v[6] = ld4_wrap(rm + 6 * plane, nx, x0 + 1);
-    v[7] = ld4_wrap(rp + 7 * plane, nx, x0 + 1);
-  }
-  float o[9][4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    float g[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = v[i][k];
-    bgk_collide(g, omega);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) o[i][k] = g[i];
-  }
-  float *d = dst + (size_t)y * nx + x0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    vf4 w = {o[i][0], o[i][1], o[i][2], o[i][3]};
-    __builtin_nontemporal_store(w, (vf4 *)(d + i * plane));
-  }
-}
-
-// Kernel choice for the FP32 step: 0 = automatic (four nodes per thread when
-// the row length allows it), 1 = one node per thread.  Read once from the
-// environment variable LBMGNN_BGK_VARIANT, for measurements.
-static int bgk_variant() {
-  static int v = [] {
-    const char *e = getenv("LBMGNN_BGK_VARIANT");
-    return e ? atoi(e) : 0;
-  }();
-  return v;
+  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(g[i], d + (size_t)i * nx);
 }
 
 template <typename T>
 int launch_bgk(const T *src, T *dst, int nx, int ny, T tau, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-    bool vec_ok = nx % 4 == 0 && nx >= 8 && ((uintptr_t)src % 16 == 0) &&
-                  ((uintptr_t)dst % 16 == 0);
-    if (vec_ok && bgk_variant() != 1) {
-      dim3 grid((nx / 4 + kVecThreads - 1) / kVecThreads, ny);
-      hipLaunchKernelGGL(bgk_pull_vec4_kernel, grid, dim3(kVecThreads), 0, s, src, dst, nx,
-                         ny, T(1) / tau);
-      return launch_check("bgk_pull_vec4_kernel");
-    }
-  }
-  dim3 grid((nx + kBgkThreads - 1) / kBgkThreads, ny);
-  hipLaunchKernelGGL(bgk_pull_kernel<T>, grid, dim3(kBgkThreads), 0, s, src, dst, nx, ny,
-                     T(1) / tau);
+  int bx = (nx + kBgkThreads - 1) / kBgkThreads;
+  long long blocks = (long long)bx * ny;
+  if (blocks > 0x7fffffffLL) return fail(LBM_EINVAL, "lbm_step_bgk: lattice too large");
+  hipLaunchKernelGGL(bgk_pull_kernel<T>, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s, src,
+                     dst, nx, ny, bx, T(1) / tau);
   return launch_check("bgk_pull_kernel");
 }
 
@@ -218,15 +110,16 @@ __global__ __launch_bounds__(kReduceThreads) void moments_kernel(
     const float *__restrict__ g, int nx, int ny, float *__restrict__ rho_out,
     float *__restrict__ ux_out, float *__restrict__ uy_out, lbm_tgv a, int with_tgv,
     double *__restrict__ partials) {
-  size_t plane = (size_t)nx * ny;
+  size_t nodes = (size_t)nx * ny;
   double acc[8] = {0, 0, 0, 0, 0, 0, INFINITY, 0};
-  for (size_t n = (size_t)blockIdx.x * kReduceThreads + threadIdx.x; n < plane;
+  for (size_t n = (size_t)blockIdx.x * kReduceThreads + threadIdx.x; n < nodes;
        n += (size_t)gridDim.x * kReduceThreads) {
+    int x = (int)(n % nx), y = (int)(n / nx);
     double f[9];
     double drho = 0, jx = 0, jy = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      double gi = (double)g[i * plane + n];
+      double gi = (double)g[pidx(nx, y, i, x)];
       f[i] = gi + wgt<double>(i);
       drho += gi;
       jx += cx(i) * gi;
@@ -243,7 +136,7 @@ __global__ __launch_bounds__(kReduceThreads) void moments_kernel(
     acc[3] += 0.5 * (u * u + v * v);
     if (with_tgv) {
       double uax, uay;
-      tgv_field(a, (int)(n % nx), (int)(n / nx), uax, uay);
+      tgv_field(a, x, y, uax, uay);
       acc[4] += (u - uax) * (u - uax) + (v - uay) * (v - uay);
       acc[5] += uax * uax + uay * uay;
     }
@@ -272,16 +165,19 @@ __global__ __launch_bounds__(kReduceThreads) void moments_finalize(
 
 // ------------------------------------------------------------ restriction ---
 
+// Fine and coarse lattices are both row-interleaved.  One thread per coarse
+// population value.
 __global__ void restrict_kernel(const double *__restrict__ gf, int nxf, int nyf, int factor,
                                 double lambda, int pull, int unstream,
                                 float *__restrict__ gc) {
   int nxc = nxf / factor, nyc = nyf / factor;
-  size_t pc = (size_t)nxc * nyc, pf = (size_t)nxf * nyf;
   size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 9 * pc) return;
-  int i = (int)(idx / pc);
-  size_t nc = idx % pc;
-  int X = (int)(nc % nxc), Y = (int)(nc / nxc);
+  if (idx >= (size_t)9 * nxc * nyc) return;
+  // idx = (Yo * 9 + i) * nxc + Xo
+  int Xo = (int)(idx % nxc);
+  size_t rest = idx / nxc;
+  int i = (int)(rest % 9), Yo = (int)(rest / 9);
+  int X = Xo, Y = Yo;
   if (unstream) {  // out_i(X) = R_i(X + e_i)
     X = (X + cx(i) + nxc) % nxc;
     Y = (Y + cy(i) + nyc) % nyc;
@@ -295,7 +191,7 @@ __global__ void restrict_kernel(const double *__restrict__ gf, int nxf, int nyf,
       xs = (xf - cx(k) + nxf) % nxf;
       ys = (yf - cy(k) + nyf) % nyf;
     }
-    f[k] = gf[k * pf + (size_t)ys * nxf + xs] + wgt<double>(k);
+    f[k] = gf[pidx(nxf, ys, k, xs)] + wgt<double>(k);
     rho += f[k];
     jx += cx(k) * f[k];
     jy += cy(k) * f[k];
@@ -323,10 +219,12 @@ __global__ void restrict_kernel(const double *__restrict__ gf, int nxf, int nyf,
 
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
+// One 16-byte element per thread, non-temporal stores: the plain streaming
+// copy that bounds what a read-once write-once kernel can reach.
 __global__ __launch_bounds__(256) void copy_kernel(const vf4 *__restrict__ src,
                                                    vf4 *__restrict__ dst, size_t n4) {
-  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n4; k += (size_t)gridDim.x * 256)
-    __builtin_nontemporal_store(src[k], &dst[k]);
+  size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n4) __builtin_nontemporal_store(src[k], &dst[k]);
 }
 
 __global__ void copy_tail_kernel(const float *__restrict__ src, float *__restrict__ dst,
@@ -347,8 +245,8 @@ static int init_impl(T *g, int nx, int ny, const T *rho, const T *ux, const T *u
   if (!g || !rho || !ux || !uy) return fail(LBM_EINVAL, "lbm_init: null pointer");
   if (!lattice_ok(nx, ny)) return fail(LBM_EINVAL, "lbm_init: bad lattice %d x %d", nx, ny);
   if (int rc = check_device()) return rc;
-  size_t plane = (size_t)nx * ny;
-  hipLaunchKernelGGL(init_kernel<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0,
+  size_t nodes = (size_t)nx * ny;
+  hipLaunchKernelGGL(init_kernel<T>, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0,
                      as_stream(stream), g, nx, ny, rho, ux, uy);
   return launch_check("init_kernel");
 }
@@ -369,8 +267,7 @@ static int step_bgk_impl(const T *src, T *dst, int nx, int ny, T tau, void *stre
   if (!lattice_ok(nx, ny)) return fail(LBM_EINVAL, "lbm_step_bgk: bad lattice %d x %d", nx, ny);
   if (!(tau > T(0))) return fail(LBM_EINVAL, "lbm_step_bgk: tau must be positive");
   size_t bytes = (size_t)9 * nx * ny * sizeof(T);
-  const char *a = (const char *)src, *b = (const char *)dst;
-  if (a < b + bytes && b < a + bytes)
+  if (overlap(src, dst, bytes))
     return fail(LBM_EINVAL, "lbm_step_bgk: source and destination overlap");
   if (int rc = check_device()) return rc;
   return launch_bgk(src, dst, nx, ny, tau, as_stream(stream));
@@ -391,15 +288,14 @@ extern "C" int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux
                            size_t ws_bytes, void *stream) {
   if (!g) return fail(LBM_EINVAL, "lbm_moments: null populations");
   if (!lattice_ok(nx, ny)) return fail(LBM_EINVAL, "lbm_moments: bad lattice %d x %d", nx, ny);
+  if (!sums && !rho && !ux && !uy) return LBM_OK;
   long long nodes = (long long)nx * ny;
   int nb = reduce_blocks(nodes);
-  if (sums) {
-    if (!workspace || ws_bytes < (size_t)nb * 8 * sizeof(double))
-      return fail(LBM_EWORKSPACE, "lbm_moments: workspace needs %zu bytes",
-                  (size_t)nb * 8 * sizeof(double));
-    if (analytic && !(analytic->ky != 0.0))
-      return fail(LBM_EINVAL, "lbm_moments: analytic field needs ky != 0");
-  }
+  size_t need = (size_t)nb * 8 * sizeof(double);
+  if (!workspace || ws_bytes < need)
+    return fail(LBM_EWORKSPACE, "lbm_moments: workspace needs %zu bytes", need);
+  if (analytic && !(analytic->ky != 0.0))
+    return fail(LBM_EINVAL, "lbm_moments: analytic field needs ky != 0");
   if (int rc = check_device()) return rc;
   lbm_tgv a{};
   int with = 0;
@@ -408,15 +304,7 @@ extern "C" int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux
     with = 1;
   }
   hipStream_t s = as_stream(stream);
-  double *part = sums ? (double *)workspace : nullptr;
-  if (!sums) {
-    // fields only: run the same kernel with a private partial buffer disabled
-    if (!rho && !ux && !uy) return LBM_OK;
-    if (!workspace || ws_bytes < (size_t)nb * 8 * sizeof(double))
-      return fail(LBM_EWORKSPACE, "lbm_moments: workspace needs %zu bytes",
-                  (size_t)nb * 8 * sizeof(double));
-    part = (double *)workspace;
-  }
+  double *part = (double *)workspace;
   hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(kReduceThreads), 0, s, g, nx, ny, rho, ux,
                      uy, a, with, part);
   if (int rc = launch_check("moments_kernel")) return rc;
@@ -447,12 +335,14 @@ extern "C" int lbm_copy(const float *src, float *dst, size_t n, void *stream) {
   if (!src || !dst) return fail(LBM_EINVAL, "lbm_copy: null pointer");
   if (((uintptr_t)src | (uintptr_t)dst) & 15)
     return fail(LBM_EINVAL, "lbm_copy: pointers must be 16-byte aligned");
+  if (overlap(src, dst, n * sizeof(float)))
+    return fail(LBM_EINVAL, "lbm_copy: source and destination overlap");
   if (int rc = check_device()) return rc;
   hipStream_t s = as_stream(stream);
   size_t n4 = n / 4;
   if (n4) {
     size_t blocks = (n4 + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    if (blocks > 0x7fffffffULL) return fail(LBM_EINVAL, "lbm_copy: too large");
     hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const vf4 *)src, (vf4 *)dst, n4);
     if (int rc = launch_check("copy_kernel")) return rc;

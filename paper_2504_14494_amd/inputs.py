@@ -49,6 +49,19 @@ def tgv_spec(nx: int, ny: int, u0: float, nu: float, t: float,
     return (u0, 2 * np.pi / nx, 2 * np.pi / ny, x0, y0, nu, t)
 
 
+def planes_to_rows(a):
+    """[..., 9, ny, nx] (one plane per direction, the oracle's order) ->
+    [..., ny, 9, nx] (row-interleaved, the library's order).  Layout only."""
+    a = np.asarray(a)
+    return np.ascontiguousarray(np.swapaxes(a, -3, -2))
+
+
+def rows_to_planes(a):
+    """Inverse of planes_to_rows."""
+    a = np.asarray(a)
+    return np.ascontiguousarray(np.swapaxes(a, -3, -2))
+
+
 def random_shifted_state(shape, amp: float, seed: int) -> np.ndarray:
     """Random shifted populations g = f - w with N(0, amp^2) entries, FP32.
     With amp <= 5e-3 every f = w + g stays positive (w >= 1/36)."""

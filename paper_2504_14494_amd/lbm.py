@@ -2,8 +2,9 @@
 
 Functions keep the C names (lbm_init, lbm_step_bgk, ...).  PyTorch supplies
 device memory and the current HIP stream; all arithmetic runs in
-liblbmgnn.so.  Populations are shifted (g = f - w) SoA tensors shaped
-[9, ny, nx] (or [batch, 9, ny, nx]).
+liblbmgnn.so.  Populations are shifted (g = f - w) row-interleaved tensors
+shaped [ny, 9, nx] (or [batch, ny, 9, nx]): for each lattice row, nine
+contiguous runs of nx values, one per direction.
 """
 from __future__ import annotations
 
@@ -38,9 +39,9 @@ def _need(t: torch.Tensor, dtype, what: str):
 
 
 def _pop_dims(g: torch.Tensor):
-    if g.dim() != 3 or g.shape[0] != 9:
-        raise ValueError(f"populations must be [9, ny, nx], got {tuple(g.shape)}")
-    return int(g.shape[2]), int(g.shape[1])
+    if g.dim() != 3 or g.shape[1] != 9:
+        raise ValueError(f"populations must be [ny, 9, nx], got {tuple(g.shape)}")
+    return int(g.shape[2]), int(g.shape[0])
 
 
 def lbm_workspace_bytes(op: int, batch: int, nx: int, ny: int, n_rounds: int = 0) -> int:
@@ -119,7 +120,7 @@ def lbm_restrict(g_fine: torch.Tensor, factor: int, tau_f: float, tau_c: float,
     _need(g_fine, torch.float64, "g_fine")
     nxf, nyf = _pop_dims(g_fine)
     if out is None:
-        out = torch.empty((9, nyf // factor, nxf // factor), dtype=torch.float32,
+        out = torch.empty((nyf // factor, 9, nxf // factor), dtype=torch.float32,
                           device=g_fine.device)
     _need(out, torch.float32, "out")
     rc = _lib.load().lbm_restrict(_ptr(g_fine), nxf, nyf, factor, float(tau_f), float(tau_c),
@@ -140,7 +141,7 @@ class Lattice:
 
     def __init__(self, nx: int, ny: int, dtype=torch.float32, device="cuda"):
         self.nx, self.ny = nx, ny
-        self.a = torch.empty((9, ny, nx), dtype=dtype, device=device)
+        self.a = torch.empty((ny, 9, nx), dtype=dtype, device=device)
         self.b = torch.empty_like(self.a)
         self.steps = 0
 

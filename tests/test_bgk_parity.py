@@ -2,6 +2,10 @@
 moments/observables and the fine-to-coarse restriction against the FP64
 oracle (paper: Eq. 1 and Eq. 2; Taylor-Green validation).
 
+Layouts: the library stores populations row-interleaved, [ny, 9, nx]; the
+oracle uses one plane per direction, [9, ny, nx].  inputs.planes_to_rows /
+rows_to_planes convert (a transpose, no arithmetic).
+
 Comparison convention: the GPU buffers hold post-collision states (fused pull
 form).  After n GPU steps from an equilibrium start the GPU holds the
 collision of the oracle's pre-collision state f_n; moments are equal on both
@@ -25,6 +29,16 @@ def _w(orc):
 
 def _gpu(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _gpu_pop(planes, dtype=torch.float32):
+    """Oracle-order populations [9, ny, nx] -> device tensor [ny, 9, nx]."""
+    return _gpu(inputs.planes_to_rows(planes), dtype)
+
+
+def _host_pop(t):
+    """Device populations [ny, 9, nx] -> float64 oracle order [9, ny, nx]."""
+    return inputs.rows_to_planes(t.double().cpu().numpy())
 
 
 def _oracle_post(orc, post0, tau, steps):
@@ -68,13 +82,13 @@ def test_tgv_64_re100_1000_steps_matches_fp64_oracle(orc):
 def test_small_and_ragged_lattices(orc, ny, nx):
     post0 = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=nx * 100 + ny)
     tau, steps = 0.61, 4
-    a = _gpu(post0)
+    a = _gpu_pop(post0)
     b = torch.full_like(a, float("nan"))
     for _ in range(steps):
         lbm.lbm_step_bgk(a, b, np.float32(tau))
         a, b = b, a
         b.fill_(float("nan"))
-    got = a.cpu().numpy().astype(np.float64)
+    got = _host_pop(a)
     assert np.isfinite(got).all()
     ref = _oracle_post(orc, post0.astype(np.float64) + _w(orc), float(np.float32(tau)), steps)
     assert np.abs(got + _w(orc) - ref).max() < 2e-7
@@ -83,23 +97,23 @@ def test_small_and_ragged_lattices(orc, ny, nx):
 def test_fp64_step_matches_oracle(orc):
     ny, nx = 17, 23
     post0 = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=7).astype(np.float64)
-    a = _gpu(post0, torch.float64)
+    a = _gpu_pop(post0, torch.float64)
     b = torch.empty_like(a)
     for _ in range(3):
         lbm.lbm_step_bgk(a, b, 0.7)
         a, b = b, a
     ref = _oracle_post(orc, post0 + _w(orc), 0.7, 3)
-    assert np.abs(a.cpu().numpy() + _w(orc) - ref).max() < 5e-15
+    assert np.abs(_host_pop(a) + _w(orc) - ref).max() < 5e-15
 
 
 def test_init_matches_oracle_equilibrium(orc):
     ny, nx = 12, 20
     rho, ux, uy = inputs.tgv_velocity(nx, ny, 0.05, x0=1.5, dtype=np.float32)
     rho = rho * np.float32(1.01)
-    g = torch.empty((9, ny, nx), device="cuda")
+    g = torch.empty((ny, 9, nx), device="cuda")
     lbm.lbm_init(g, _gpu(rho), _gpu(ux), _gpu(uy))
     ref = orc.init_equilibrium(rho, ux, uy)
-    assert np.abs(g.cpu().numpy() + _w(orc) - ref).max() < 1e-8
+    assert np.abs(_host_pop(g) + _w(orc) - ref).max() < 1e-8
 
 
 def test_moments_and_observables(orc):
@@ -107,7 +121,7 @@ def test_moments_and_observables(orc):
     g = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=11)
     g[3, 5, 7] = -0.5                                   # one negative population
     spec = inputs.tgv_spec(nx, ny, 0.03, 0.01, 37.0, x0=0.3, y0=-2.0)
-    r, ux, uy, sums = lbm.lbm_moments(_gpu(g), spec, fields=True)
+    r, ux, uy, sums = lbm.lbm_moments(_gpu_pop(g), spec, fields=True)
     f = g.astype(np.float64) + _w(orc)
     ro, uxo, uyo = orc.moments(f)
     assert np.abs(r.cpu().numpy() - ro).max() < 1e-6
@@ -119,7 +133,7 @@ def test_moments_and_observables(orc):
 
 
 def test_aliasing_is_rejected():
-    a = torch.zeros((9, 8, 8), device="cuda")
+    a = torch.zeros((8, 9, 8), device="cuda")
     with pytest.raises(lbm._lib.LbmError):
         lbm.lbm_step_bgk(a, a, 0.7)
 
@@ -128,12 +142,12 @@ def test_aliasing_is_rejected():
 def test_restriction_matches_oracle(orc, pull, unstream):
     nf, factor = 32, 4
     gf = inputs.random_shifted_state((9, nf, nf), 3e-3, seed=21).astype(np.float64)
-    out = lbm.lbm_restrict(_gpu(gf, torch.float64), factor, 0.56, 0.515, pull, unstream)
+    out = lbm.lbm_restrict(_gpu_pop(gf, torch.float64), factor, 0.56, 0.515, pull, unstream)
     f = gf + _w(orc)
     if pull:
         f = orc.stream(f)
     ref = orc.restrict(f, factor, 0.56, 0.515, unstream_=bool(unstream))
-    assert np.abs(out.cpu().numpy().astype(np.float64) + _w(orc) - ref).max() < 1e-8
+    assert np.abs(_host_pop(out) + _w(orc) - ref).max() < 1e-8
 
 
 def test_full_size_8192_sampled_rows(orc):
@@ -142,18 +156,17 @@ def test_full_size_8192_sampled_rows(orc):
     n = 8192
     tau = np.float32(inputs.tgv_params(n, 0.04, 1000.0)[1])
     gen = torch.Generator(device="cuda").manual_seed(5)
-    src = (torch.randn((9, n, n), device="cuda", generator=gen) * 4e-3)
+    src = (torch.randn((n, 9, n), device="cuda", generator=gen) * 4e-3)
     dst = torch.full_like(src, float("nan"))
     lbm.lbm_step_bgk(src, dst, tau)
     assert not torch.isnan(dst).any().item()
     w = _w(orc)
-    w2 = w[:, :, 0]                                      # (9, 1) for one row
     errs = {}
     for y in (0, 1, 7, 1000, 2047, 2048, 4095, 4096, 6001, 8000, 8190, 8191):
         rows = [(y - 1) % n, y, (y + 1) % n]
-        band = src[:, rows, :].double().cpu().numpy() + w
+        band = _host_pop(src[rows]) + w                  # [9, 3, n]
         ref = orc.collide_bgk(orc.stream(band), float(tau))[:, 1, :]
-        got = dst[:, y, :].double().cpu().numpy() + w2
+        got = dst[y].double().cpu().numpy() + w[:, :, 0]  # [9, n]
         e = np.abs(got - ref)
         errs[y] = (float(e.max()), np.unravel_index(int(e.argmax()), e.shape))
     print("max error per checked row (value, (direction, x)):", errs)
