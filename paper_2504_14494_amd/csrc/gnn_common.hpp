@@ -1,0 +1,156 @@
+// Device building blocks of the GNN-corrected collision on gfx950:
+// BF16 fragments for v_mfma_f32_16x16x32_bf16, the activation functions and
+// the packed weight-fragment buffer written by gnn_prep_kernel.
+//
+// Orientation.  Every dense layer is computed transposed, out^T = W in^T:
+// the 16x16 MFMA tile has output channels as rows (M) and nodes as columns
+// (N), and the contraction runs over input channels (K).  A wave therefore
+// processes 16 nodes at a time and holds, after an MFMA, in lane l = 16 q + n
+// (n = node 0..15, q = 0..3) the outputs of channels 16 t + 4 q + e (e = 0..3)
+// of row tile t.  The B operand of a 16x16x32 step holds, in the same lane,
+// 8 input values of node n.  Choosing the 8 values of k-step s to be the
+// outputs of row tiles 2s and 2s+1 of the previous layer, i.e. input channel
+//     c(s, q, j) = 16 (2 s + j / 4) + 4 q + j % 4,     j = 0..7,
+// makes a layer's FP32 accumulators, rounded to BF16, exactly the next
+// layer's B operand: layers chain in registers with no data movement.  The
+// weights (A operand) are stored with their input columns permuted the same
+// way.  Node states stored in memory use this "fragment order": position
+// p = 32 s + 8 q + j of a node's 64 values holds channel c(s, q, j).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gnn_layout.hpp"
+
+namespace gnn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Input channel (natural index) behind element j of k-step s in lane group q.
+__host__ __device__ constexpr int frag_channel(int s, int q, int j) {
+  return 16 * (2 * s + j / 4) + 4 * q + (j % 4);
+}
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Two FP32 values rounded to nearest-even BF16, packed low/high
+// (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  __bf16 a = (__bf16)lo, b = (__bf16)hi;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) {
+  return __uint_as_float(bits16 << 16);
+}
+
+// B-operand fragment of k-step s from the FP32 accumulators of row tiles
+// 2s and 2s+1.
+__device__ __forceinline__ u32x4 frag_from_acc(f32x4 lo, f32x4 hi) {
+  u32x4 r;
+  r.x = pack_bf16(lo.x, lo.y);
+  r.y = pack_bf16(lo.z, lo.w);
+  r.z = pack_bf16(hi.x, hi.y);
+  r.w = pack_bf16(hi.z, hi.w);
+  return r;
+}
+
+// GELU, tanh form: 0.5 x (1 + tanh(k0 (x + k1 x^3))) = x / (1 + 2^t) with
+// t = -2 k0 log2(e) (x + k1 x^3).  One hardware exp2 and one reciprocal.
+constexpr float kGeluA = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+constexpr float kGeluB = kGeluA * 0.044715f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+__device__ __forceinline__ float gelu(float x) {
+  float t = x * __builtin_fmaf(x * x, kGeluB, kGeluA);
+  float e = __builtin_amdgcn_exp2f(t);
+  return x * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// d GELU / dx = s - x s (1 - s) ln2 (A + 3 B x^2), s = 1 / (1 + 2^t).
+__device__ __forceinline__ float gelu_grad(float x) {
+  float x2 = x * x;
+  float t = x * __builtin_fmaf(x2, kGeluB, kGeluA);
+  float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
+  float dt = __builtin_fmaf(x2, 3.0f * kGeluB, kGeluA) * kLn2;
+  return s - x * s * (1.0f - s) * dt;
+}
+
+__device__ __forceinline__ f32x4 gelu4(f32x4 v) {
+  return f32x4{gelu(v.x), gelu(v.y), gelu(v.z), gelu(v.w)};
+}
+
+// ------------------------------------------------------------------------
+// Packed weights.  gnn_prep_kernel converts the FP32 blob into BF16
+// A-operand fragments (1 KiB each: 64 lanes x 16 B) and FP32 bias fragments
+// in accumulator layout (1 KiB each: 64 lanes x 4 floats).  Forward
+// fragments first; the transposed weights used by the backward pass follow.
+// ------------------------------------------------------------------------
+struct FragLayout {
+  // A-operand fragments, index of (tile, k-step) 0
+  int W1, W2, WA[MAX_ROUNDS], WB[MAX_ROUNDS], WC[MAX_ROUNDS], WN[MAX_ROUNDS], WH;
+  // transposed weights for the backward pass
+  int W2T, WAT[MAX_ROUNDS], WBT[MAX_ROUNDS], WNT[MAX_ROUNDS], WHT;
+  int nfrag;
+  // bias fragments
+  int B1, B2, BE[MAX_ROUNDS], BN[MAX_ROUNDS], BH;
+  int nbias;
+  // byte offsets inside the packed buffer
+  size_t frag_off, bias_off, const_off, total;
+};
+
+__host__ __device__ inline FragLayout frag_layout(int R) {
+  FragLayout F{};
+  int f = 0;
+  F.W1 = f; f += 4;          // 4 row tiles x 1 k-step (K = 12 padded to 32)
+  F.W2 = f; f += 8;          // 4 x 2
+  for (int r = 0; r < R; ++r) {
+    F.WA[r] = f; f += 8;     // 4 x 2   receiver part of the edge layer
+    F.WB[r] = f; f += 8;     // 4 x 2   sender part
+    F.WC[r] = f; f += 4;     // 4 x 1   edge-direction part (K = 2 padded)
+    F.WN[r] = f; f += 16;    // 4 x 4   node update, K = 128
+  }
+  F.WH = f; f += 2;          // 1 x 2   head (10 rows padded to 16)
+  F.W2T = f; f += 8;         // W2^T       4 x 2
+  for (int r = 0; r < R; ++r) {
+    F.WAT[r] = f; f += 8;    // Wa^T       4 x 2
+    F.WBT[r] = f; f += 8;    // Wb^T       4 x 2
+    F.WNT[r] = f; f += 16;   // Wn^T       8 x 2 (128 rows)
+  }
+  F.WHT = f; f += 4;         // Wh^T       4 x 1 (K = 10 padded to 32)
+  F.nfrag = f;
+  int b = 0;
+  F.B1 = b; b += 4;
+  F.B2 = b; b += 4;
+  for (int r = 0; r < R; ++r) {
+    F.BE[r] = b; b += 4;
+    F.BN[r] = b; b += 4;
+  }
+  F.BH = b; b += 1;
+  F.nbias = b;
+  F.frag_off = 0;
+  F.bias_off = (size_t)F.nfrag * 1024;
+  F.const_off = F.bias_off + (size_t)F.nbias * 1024;
+  F.total = align256(F.const_off + 32 * sizeof(float));
+  return F;
+}
+
+// Constants after the bias fragments (FP32): mu[12], sigma[12], s_delta.
+constexpr int C_MU = 0, C_SIGMA = 12, C_SDELTA = 24;
+
+__device__ __forceinline__ u32x4 load_frag(const u32x4 *__restrict__ frags, int f, int lane) {
+  return frags[(size_t)f * 64 + lane];
+}
+__device__ __forceinline__ f32x4 load_bias(const f32x4 *__restrict__ bias, int b, int lane) {
+  return bias[(size_t)b * 64 + lane];
+}
+
+}  // namespace gnn

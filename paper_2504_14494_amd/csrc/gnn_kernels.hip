@@ -1,25 +1,797 @@
-// GNN-corrected collision (placeholder entry points until the kernels land).
-#include "gnn_layout.hpp"
+// GNN-corrected collision (Eq. 3) on gfx950: weight packing, the node
+// encoder, message-passing rounds with the head, projection and corrected
+// collision fused into the last round, and the device-side fallback gate.
+//
+// Network (per node; sizes of the 2048^2 inference workload):
+//   x  = (g_0..g_8, rho - 1, u_x, u_y), normalised (x - mu) / sigma      12
+//   h0 = GELU(W2 GELU(W1 x + b1) + b2)                          12 -> 64 -> 64
+//   round r: m_d = GELU(We [h_n; h_{n+e_d}; e_d] + be) for the 8 neighbours,
+//            a = sum_d m_d,  h' = GELU(Wn [h_n; a] + bn)       130 -> 64, 128 -> 64
+//   z  = Wh h_R + bh                                                  64 -> 10
+//   tau_adj = 1/2 + sigmoid(z_0),  delta f = s_delta P z_{1..9}
+//   f*_i = f_i - (f_i - f_i^eq) / (tau tau_adj) + delta f_i                (Eq. 3)
+// P is the orthogonal projector onto the null space of the mass and momentum
+// moments: with M = [1; e_x; e_y], M M^T = diag(9, 6, 6), so
+// (P v)_i = v_i - m0/9 - e_ix mx/6 - e_iy my/6 for the moments (m0, mx, my)
+// of v.
+//
+// The edge layer is split exactly, We [h_n; h_j; e_d] = Wa h_n + Wb h_j +
+// Wc e_d: the receiver part Wa h_n + be is formed once per node and seeds the
+// accumulator of each of the 8 edges, which then add Wc e_d and Wb h_j with
+// MFMA.  All dense layers are BF16 x BF16 -> FP32 MFMA (16x16x32); GELU,
+// the message sum and everything after the head run in FP32 on the VALU.
+#include <cstdio>
+
+#include "gnn_common.hpp"
 #include "lbm_common.hpp"
 
-using namespace lbm;
+namespace gnn {
+
+using lbm::cx;
+using lbm::cy;
+
+// ------------------------------------------------------------ packing ---
+
+// One thread per (fragment, lane): 8 BF16 A-operand values (or, for bias
+// fragments, 4 FP32 accumulator-layout values).  See gnn_common.hpp for the
+// fragment conventions.
+__device__ float frag_value(const float *__restrict__ blob, const BlobLayout &L,
+                            const FragLayout &F, int R, int f, int lane, int j) {
+  int m = lane & 15, q = lane >> 4;
+  if (f >= F.W1 && f < F.W1 + 4) {
+    int t = f - F.W1, k = 8 * q + j;
+    return k < NFEAT ? blob[L.W1 + (size_t)(16 * t + m) * NFEAT + k] : 0.0f;
+  }
+  if (f >= F.W2 && f < F.W2 + 8) {
+    int t = (f - F.W2) >> 1, s = (f - F.W2) & 1;
+    return blob[L.W2 + (size_t)(16 * t + m) * HID + frag_channel(s, q, j)];
+  }
+  if (f >= F.WH && f < F.WH + 2) {
+    int s = f - F.WH;
+    return m < NOUT ? blob[L.Wh + (size_t)m * HID + frag_channel(s, q, j)] : 0.0f;
+  }
+  if (f >= F.W2T && f < F.W2T + 8) {  // rows: e1 channels, k: h0 channels
+    int t = (f - F.W2T) >> 1, s = (f - F.W2T) & 1;
+    return blob[L.W2 + (size_t)frag_channel(s, q, j) * HID + 16 * t + m];
+  }
+  if (f >= F.WHT && f < F.WHT + 4) {  // rows: h_R channels, k: head outputs
+    int t = f - F.WHT, k = 8 * q + j;
+    return k < NOUT ? blob[L.Wh + (size_t)k * HID + 16 * t + m] : 0.0f;
+  }
+  for (int r = 0; r < R; ++r) {
+    const size_t We = L.We[r], Wn = L.Wn[r];
+    if (f >= F.WA[r] && f < F.WA[r] + 8) {
+      int t = (f - F.WA[r]) >> 1, s = (f - F.WA[r]) & 1;
+      return blob[We + (size_t)(16 * t + m) * EDGE_IN + frag_channel(s, q, j)];
+    }
+    if (f >= F.WB[r] && f < F.WB[r] + 8) {
+      int t = (f - F.WB[r]) >> 1, s = (f - F.WB[r]) & 1;
+      return blob[We + (size_t)(16 * t + m) * EDGE_IN + HID + frag_channel(s, q, j)];
+    }
+    if (f >= F.WC[r] && f < F.WC[r] + 4) {
+      int t = f - F.WC[r];
+      return (q == 0 && j < 2) ? blob[We + (size_t)(16 * t + m) * EDGE_IN + 2 * HID + j] : 0.0f;
+    }
+    if (f >= F.WN[r] && f < F.WN[r] + 16) {
+      int t = (f - F.WN[r]) >> 2, s = (f - F.WN[r]) & 3;
+      int c = s < 2 ? frag_channel(s, q, j) : HID + frag_channel(s - 2, q, j);
+      return blob[Wn + (size_t)(16 * t + m) * NODE_IN + c];
+    }
+    if (f >= F.WAT[r] && f < F.WAT[r] + 8) {
+      int t = (f - F.WAT[r]) >> 1, s = (f - F.WAT[r]) & 1;
+      return blob[We + (size_t)frag_channel(s, q, j) * EDGE_IN + 16 * t + m];
+    }
+    if (f >= F.WBT[r] && f < F.WBT[r] + 8) {
+      int t = (f - F.WBT[r]) >> 1, s = (f - F.WBT[r]) & 1;
+      return blob[We + (size_t)frag_channel(s, q, j) * EDGE_IN + HID + 16 * t + m];
+    }
+    if (f >= F.WNT[r] && f < F.WNT[r] + 16) {  // 8 row tiles (h then a) x 2 k-steps
+      int t = (f - F.WNT[r]) >> 1, s = (f - F.WNT[r]) & 1;
+      return blob[Wn + (size_t)frag_channel(s, q, j) * NODE_IN + 16 * t + m];
+    }
+  }
+  return 0.0f;
+}
+
+__device__ float bias_value(const float *__restrict__ blob, const BlobLayout &L,
+                            const FragLayout &F, int R, int b, int lane, int e) {
+  int q = lane >> 4;
+  if (b == F.BH) {
+    int k = 4 * q + e;
+    return k < NOUT ? blob[L.bh + k] : 0.0f;
+  }
+  int t, base;
+  if (b >= F.B1 && b < F.B1 + 4) {
+    t = b - F.B1;
+    base = (int)L.b1;
+  } else if (b >= F.B2 && b < F.B2 + 4) {
+    t = b - F.B2;
+    base = (int)L.b2;
+  } else {
+    base = -1;
+    t = 0;
+    for (int r = 0; r < R; ++r) {
+      if (b >= F.BE[r] && b < F.BE[r] + 4) {
+        t = b - F.BE[r];
+        base = (int)L.be[r];
+      }
+      if (b >= F.BN[r] && b < F.BN[r] + 4) {
+        t = b - F.BN[r];
+        base = (int)L.bn[r];
+      }
+    }
+    if (base < 0) return 0.0f;
+  }
+  return blob[base + 16 * t + 4 * q + e];
+}
+
+__global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ blob, int R,
+                                                      BlobLayout L, FragLayout F,
+                                                      uint8_t *__restrict__ pack) {
+  int lane = threadIdx.x, f = blockIdx.x;
+  if (f < F.nfrag) {
+    u32x4 v;
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      w[k] = pack_bf16(frag_value(blob, L, F, R, f, lane, 2 * k),
+                       frag_value(blob, L, F, R, f, lane, 2 * k + 1));
+    v = u32x4{w[0], w[1], w[2], w[3]};
+    ((u32x4 *)(pack + F.frag_off))[(size_t)f * 64 + lane] = v;
+  } else if (f < F.nfrag + F.nbias) {
+    int b = f - F.nfrag;
+    f32x4 v;
+    v.x = bias_value(blob, L, F, R, b, lane, 0);
+    v.y = bias_value(blob, L, F, R, b, lane, 1);
+    v.z = bias_value(blob, L, F, R, b, lane, 2);
+    v.w = bias_value(blob, L, F, R, b, lane, 3);
+    ((f32x4 *)(pack + F.bias_off))[(size_t)b * 64 + lane] = v;
+  } else if (lane < 25) {
+    ((float *)(pack + F.const_off))[lane] = blob[L.mu + lane];
+  }
+}
+
+// ------------------------------------------------------------ encoder ---
+
+// Shifted populations of node (x, y) of lattice `lat`: pulled through one
+// streaming step from a post-collision state, or read in place.
+template <bool PULL>
+__device__ __forceinline__ void node_pops(const float *__restrict__ lat, int nx, int ny, int x,
+                                          int y, float (&g)[9]) {
+  if constexpr (PULL) {
+    lbm::pull9(lat, nx, ny, x, y, g);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = lat[lbm::pidx(nx, y, i, x)];
+  }
+}
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// One wave per group of 16 consecutive nodes of a lattice row; groups are
+// taken grid-stride.  Lanes with x >= nx (ragged row end) compute on a
+// wrapped node and store nothing.
+template <bool PULL, bool SAVE>
+__global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
+    const float *__restrict__ g, int batch, int nx, int ny, const uint8_t *__restrict__ pack,
+    FragLayout F, uint16_t *__restrict__ h0, uint16_t *__restrict__ save_x,
+    uint16_t *__restrict__ save_e1) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 15, q = lane >> 4;
+  const u32x4 *frags = (const u32x4 *)(pack + F.frag_off);
+  const f32x4 *bias = (const f32x4 *)(pack + F.bias_off);
+  const float *cst = (const float *)(pack + F.const_off);
+  u32x4 w1[4], w2[4][2];
+  f32x4 b1[4], b2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    w1[t] = load_frag(frags, F.W1 + t, lane);
+    w2[t][0] = load_frag(frags, F.W2 + 2 * t, lane);
+    w2[t][1] = load_frag(frags, F.W2 + 2 * t + 1, lane);
+    b1[t] = load_bias(bias, F.B1 + t, lane);
+    b2[t] = load_bias(bias, F.B2 + t, lane);
+  }
+  // Normalisation constants of the 8 features this lane feeds (k = 8q + j).
+  float mu[8], sg[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int k = 8 * q + j;
+    mu[j] = k < NFEAT ? cst[C_MU + k] : 0.0f;
+    sg[j] = k < NFEAT ? cst[C_SIGMA + k] : 1.0f;
+  }
+  const long long gxn = (nx + 15) / 16;
+  const long long ngroups = (long long)batch * ny * gxn;
+  for (long long grp = (long long)blockIdx.x * kWaves + wave; grp < ngroups;
+       grp += (long long)gridDim.x * kWaves) {
+    int xg = (int)(grp % gxn);
+    long long by = grp / gxn;
+    int y = (int)(by % ny), b = (int)(by / ny);
+    int x = xg * 16 + n;
+    bool valid = x < nx;
+    int xc = valid ? x : x % nx;
+    float feat[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) feat[j] = 0.0f;
+    if (q < 2) {
+      float gp[9];
+      node_pops<PULL>(g + (size_t)b * ny * 9 * nx, nx, ny, xc, y, gp);
+      float drho, rho, u, v, uu;
+      lbm::node_moments(gp, drho, rho, u, v, uu);
+      const float all[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
+                                gp[6], gp[7], gp[8], drho, u,     v};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        float raw = q == 0 ? all[j] : (j < NFEAT - 8 ? all[8 + (j < NFEAT - 8 ? j : 0)] : 0.0f);
+        feat[j] = (q == 0 || j < NFEAT - 8) ? (raw - mu[j]) / sg[j] : 0.0f;
+      }
+    }
+    u32x4 xb = {pack_bf16(feat[0], feat[1]), pack_bf16(feat[2], feat[3]),
+                pack_bf16(feat[4], feat[5]), pack_bf16(feat[6], feat[7])};
+    f32x4 a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = gelu4(mfma(w1[t], xb, b1[t]));
+    u32x4 e1[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f32x4 acc = mfma(w2[t][0], e1[0], b2[t]);
+      a[t] = gelu4(mfma(w2[t][1], e1[1], acc));
+    }
+    u32x4 hb[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
+    if (valid) {
+      size_t node = ((size_t)b * ny + y) * nx + x;
+      u32x4 *dst = (u32x4 *)(h0 + node * HID);
+      dst[q] = hb[0];
+      dst[4 + q] = hb[1];
+      if constexpr (SAVE) {
+        if (q < 2) ((u32x4 *)(save_x + node * 16))[q] = xb;
+        u32x4 *de = (u32x4 *)(save_e1 + node * HID);
+        de[q] = e1[0];
+        de[4 + q] = e1[1];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------- message passing round ---
+
+constexpr int TILE = 16;            // receivers per tile edge
+constexpr int HALO = TILE + 2;      // node states of the tile and its 1-node ring
+constexpr int HNODES = HALO * HALO;
+
+// BF16 bits of a small integer in {-1, 0, 1}.
+__host__ __device__ constexpr uint32_t bf16_unit(int v) {
+  return v == 0 ? 0u : (v > 0 ? 0x3f80u : 0xbf80u);
+}
+
+// Node state fragment (k-step s, lane group q) of LDS node ln.  The 8
+// 16-byte chunks of a node are XOR-swizzled with the node index so that
+// 16 lanes reading the same chunk of 16 consecutive nodes spread over banks.
+__device__ __forceinline__ u32x4 lds_frag(const uint8_t *hs, int ln, int chunk) {
+  return *(const u32x4 *)(hs + ln * 128 + ((chunk ^ (ln & 7)) << 4));
+}
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+struct HeadArgs {
+  const float *src;       // populations the collision starts from
+  float *dst;             // corrected post-collision populations
+  const float *tau_arr;   // per-lattice tau (device) or NULL
+  float tau;              // tau when tau_arr is NULL
+  float *head_out;        // [N][10] head outputs or NULL
+  float *save_z;          // [N][12] head outputs kept for the backward pass
+  double *pmass;          // [gridDim.x] FP64 sum of g* over the nodes of a workgroup
+  unsigned *pflag;        // [gridDim.x] 1 if a population came out negative / non-finite
+};
+
+// Corrected collision of one node (Eq. 3 with the projected correction).
+__device__ __forceinline__ void gnn_collide(float (&g)[9], const float (&z)[NOUT], float tau,
+                                           float sdelta) {
+  float drho, rho, u, v, uu;
+  lbm::node_moments(g, drho, rho, u, v, uu);
+  float sig = 1.0f / (1.0f + expf(-z[0]));
+  float tau_adj = 0.5f + sig;
+  float omega = 1.0f / (tau * tau_adj);
+  float m0 = 0.0f, mx = 0.0f, my = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    m0 += z[1 + i];
+    mx += float(cx(i)) * z[1 + i];
+    my += float(cy(i)) * z[1 + i];
+  }
+  m0 *= (1.0f / 9.0f);
+  mx *= (1.0f / 6.0f);
+  my *= (1.0f / 6.0f);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    float relaxed = g[i] + omega * (lbm::geq_shifted<float>(i, drho, rho, u, v, uu) - g[i]);
+    float df = z[1 + i] - m0 - float(cx(i)) * mx - float(cy(i)) * my;
+    g[i] = relaxed + sdelta * df;
+  }
+}
+
+// One round over 16 x 16 receiver tiles taken grid-stride.  The workgroup
+// stages the node states of the tile and its ring (18 x 18 nodes, BF16) in
+// LDS; wave w handles tile rows 4w..4w+3, 16 receivers (one MFMA column
+// block) at a time.  With HEAD the round is the last one: the head, the
+// projection and the corrected collision follow, written to args.dst.
+// Register budget (two waves per SIMD): only the sender weights Wb, used 8
+// times per receiver, stay in VGPRs; Wa, Wn, the head and the biases are read
+// from LDS where they are used.
+template <bool HEAD, bool PULL, bool SAVE>
+__global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
+    const uint16_t *__restrict__ hin, uint16_t *__restrict__ hout,
+    uint16_t *__restrict__ save_agg, int batch, int nx, int ny, int round,
+    const uint8_t *__restrict__ pack, FragLayout F, HeadArgs args) {
+  __shared__ __attribute__((aligned(16))) uint8_t hs[HNODES * 128];
+  __shared__ u32x4 wa_s[8 * 64];
+  __shared__ u32x4 wn_s[16 * 64];
+  __shared__ float zb[HEAD ? kWaves * 64 * NOUT : 1];
+  __shared__ double red_m[kThreads];
+  __shared__ unsigned red_f[kThreads];
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 15, q = lane >> 4;
+  const u32x4 *frags = (const u32x4 *)(pack + F.frag_off);
+  const f32x4 *bias = (const f32x4 *)(pack + F.bias_off);
+  const float *cst = (const float *)(pack + F.const_off);
+
+  for (int k = threadIdx.x; k < 8 * 64; k += kThreads)
+    wa_s[k] = frags[(size_t)F.WA[round] * 64 + k];
+  for (int k = threadIdx.x; k < 16 * 64; k += kThreads)
+    wn_s[k] = frags[(size_t)F.WN[round] * 64 + k];
+  u32x4 wb[4][2];
+  uint32_t wc[4];  // only lanes q == 0 hold a non-zero (first) dword
+  f32x4 be[4], bn[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    wb[t][0] = load_frag(frags, F.WB[round] + 2 * t, lane);
+    wb[t][1] = load_frag(frags, F.WB[round] + 2 * t + 1, lane);
+    wc[t] = load_frag(frags, F.WC[round] + t, lane).x;
+    be[t] = load_bias(bias, F.BE[round] + t, lane);
+    bn[t] = load_bias(bias, F.BN[round] + t, lane);
+  }
+  float sdelta = 0.0f;
+  u32x4 wh[2];
+  f32x4 bh;
+  if constexpr (HEAD) {
+    wh[0] = load_frag(frags, F.WH, lane);
+    wh[1] = load_frag(frags, F.WH + 1, lane);
+    bh = load_bias(bias, F.BH, lane);
+    sdelta = cst[C_SDELTA];
+  }
+
+  const int txn = (nx + TILE - 1) / TILE, tyn = (ny + TILE - 1) / TILE;
+  const long long ntiles = (long long)batch * txn * tyn;
+  double mass_acc = 0.0;
+  unsigned flag_acc = 0;
+
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tx = (int)(tile % txn);
+    const long long rest = tile / txn;
+    const int ty = (int)(rest % tyn), b = (int)(rest / tyn);
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const size_t lat_nodes = (size_t)b * ny * nx;
+
+    __syncthreads();  // weights staged / previous tile no longer read
+    for (int k = threadIdx.x; k < HNODES * 8; k += kThreads) {
+      int ln = k >> 3, c = k & 7;
+      int gx = wrapi(x0 - 1 + ln % HALO, nx), gy = wrapi(y0 - 1 + ln / HALO, ny);
+      const u32x4 *srcp = (const u32x4 *)(hin + (lat_nodes + (size_t)gy * nx + gx) * HID);
+      *(u32x4 *)(hs + ln * 128 + ((c ^ (ln & 7)) << 4)) = srcp[c];
+    }
+    __syncthreads();
+
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      // An offset the compiler cannot see through, so that the LDS weight
+      // reads below stay inside the loop instead of being hoisted into
+      // registers (which would halve the waves per SIMD).
+      int wo = lane;
+      asm volatile("" : "+v"(wo));
+      const u32x4 *wa = wa_s + wo, *wn = wn_s + wo;
+      const int tyl = wave * 4 + r;
+      const int x = x0 + n, y = y0 + tyl;
+      const int ln_self = (tyl + 1) * HALO + n + 1;
+      u32x4 hn[2] = {lds_frag(hs, ln_self, q), lds_frag(hs, ln_self, 4 + q)};
+      f32x4 an[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        an[t] = mfma(wa[(2 * t) * 64], hn[0], be[t]);
+        an[t] = mfma(wa[(2 * t + 1) * 64], hn[1], an[t]);
+      }
+      f32x4 agg[4] = {};
+#pragma unroll 2
+      for (int d = 1; d < 9; ++d) {
+        const int ln = ln_self + cy(d) * HALO + cx(d);
+        u32x4 hj[2] = {lds_frag(hs, ln, q), lds_frag(hs, ln, 4 + q)};
+        const u32x4 ed = {q == 0 ? (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)) : 0u, 0u, 0u,
+                          0u};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          f32x4 acc = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
+          acc = mfma(wb[t][0], hj[0], acc);
+          acc = mfma(wb[t][1], hj[1], acc);
+          agg[t] += gelu4(acc);
+        }
+      }
+      u32x4 ab[2] = {frag_from_acc(agg[0], agg[1]), frag_from_acc(agg[2], agg[3])};
+      f32x4 p[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        p[t] = mfma(wn[(4 * t) * 64], hn[0], bn[t]);
+        p[t] = mfma(wn[(4 * t + 1) * 64], hn[1], p[t]);
+        p[t] = mfma(wn[(4 * t + 2) * 64], ab[0], p[t]);
+        p[t] = mfma(wn[(4 * t + 3) * 64], ab[1], p[t]);
+        p[t] = gelu4(p[t]);
+      }
+      u32x4 hb[2] = {frag_from_acc(p[0], p[1]), frag_from_acc(p[2], p[3])};
+      if (x < nx && y < ny) {
+        const size_t node = lat_nodes + (size_t)y * nx + x;
+        if (hout) {
+          u32x4 *dst = (u32x4 *)(hout + node * HID);
+          dst[q] = hb[0];
+          dst[4 + q] = hb[1];
+        }
+        if constexpr (SAVE) {
+          u32x4 *da = (u32x4 *)(save_agg + node * HID);
+          da[q] = ab[0];
+          da[4 + q] = ab[1];
+        }
+      }
+      if constexpr (HEAD) {
+        f32x4 z = mfma(wh[0], hb[0], bh);
+        z = mfma(wh[1], hb[1], z);
+        float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int k = 4 * q + e;
+          if (k < NOUT) zb[(wave * 64 + r * 16 + n) * NOUT + k] = zz[e];
+        }
+      }
+    }
+
+    if constexpr (HEAD) {
+      __syncthreads();
+      // lane -> node (n, row r = lane / 16) of this wave's four tile rows
+      const int x = x0 + n, y = y0 + wave * 4 + q;
+      if (x < nx && y < ny) {
+        float z[NOUT];
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k) z[k] = zb[(wave * 64 + lane) * NOUT + k];
+        const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
+        const size_t lat_off = (size_t)b * ny * 9 * nx;
+        float gp[9];
+        node_pops<PULL>(args.src + lat_off, nx, ny, x, y, gp);
+        gnn_collide(gp, z, tau, sdelta);
+        float *d = args.dst + lat_off + (size_t)y * 9 * nx + x;
+        double msum = 0.0;
+        unsigned bad = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
+          float f = gp[i] + lbm::wgt<float>(i);
+          bad |= (f >= 0.0f && f < INFINITY) ? 0u : 1u;
+          msum += (double)gp[i];
+        }
+        mass_acc += msum;
+        flag_acc |= bad;
+        const size_t node = lat_nodes + (size_t)y * nx + x;
+        if (args.head_out)
+          for (int k = 0; k < NOUT; ++k) args.head_out[node * NOUT + k] = z[k];
+        if constexpr (SAVE)
+          for (int k = 0; k < NOUT; ++k) args.save_z[node * 12 + k] = z[k];
+      }
+    }
+  }
+
+  if constexpr (HEAD) {
+    red_m[threadIdx.x] = mass_acc;
+    red_f[threadIdx.x] = flag_acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        red_m[threadIdx.x] += red_m[threadIdx.x + s];
+        red_f[threadIdx.x] |= red_f[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      args.pmass[blockIdx.x] = red_m[0];
+      args.pflag[blockIdx.x] = red_f[0];
+    }
+  }
+}
+
+// ------------------------------------------------------------ fallback ---
+
+// Sums the per-workgroup partials of the corrected step in a fixed order and
+// decides whether the step falls back: bit 1 = a negative or non-finite
+// population, bit 2 = relative change of total mass not <= threshold.
+__global__ __launch_bounds__(kThreads) void gate_decide_kernel(
+    const double *__restrict__ pmass, const unsigned *__restrict__ pflag, int nparts,
+    double nodes, double threshold, unsigned *__restrict__ flags,
+    unsigned *__restrict__ n_fallback, double *__restrict__ mass, unsigned *__restrict__ ctrl) {
+  __shared__ double sm[kThreads];
+  __shared__ unsigned sf[kThreads];
+  double m = 0.0;
+  unsigned f = 0;
+  for (int k = threadIdx.x; k < nparts; k += kThreads) {
+    m += pmass[k];
+    f |= pflag[k];
+  }
+  sm[threadIdx.x] = m;
+  sf[threadIdx.x] = f;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] += sm[threadIdx.x + s];
+      sf[threadIdx.x] |= sf[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double mnew = nodes + sm[0];
+    double mold = *mass;
+    unsigned fl = sf[0] ? 1u : 0u;
+    double rel = fabs(mnew - mold) / mold;
+    if (!(rel <= threshold)) fl |= 2u;
+    ctrl[0] = fl;
+    if (fl) {
+      *flags |= fl;
+      if (n_fallback) *n_fallback += 1u;
+    } else {
+      *mass = mnew;
+    }
+  }
+}
+
+// Plain BGK step from the unchanged source when the gate tripped (same
+// arithmetic as bgk_pull_kernel, grid-stride); exits at once otherwise.
+__global__ __launch_bounds__(kThreads) void gate_fallback_kernel(
+    const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, float omega,
+    const unsigned *__restrict__ ctrl, double *__restrict__ pmass2) {
+  __shared__ double sm[kThreads];
+  if (ctrl[0] == 0) return;
+  double m = 0.0;
+  const size_t nodes = (size_t)nx * ny;
+  for (size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x; k < nodes;
+       k += (size_t)gridDim.x * kThreads) {
+    int x = (int)(k % nx), y = (int)(k / nx);
+    float g[9];
+    lbm::pull9(src, nx, ny, x, y, g);
+    lbm::bgk_collide(g, omega);
+    float *d = dst + (size_t)y * 9 * nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      d[(size_t)i * nx] = g[i];
+      m += (double)g[i];
+    }
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pmass2[blockIdx.x] = sm[0];
+}
+
+// After a fallback: the mass of the state actually written.
+__global__ __launch_bounds__(kThreads) void gate_mass_kernel(const double *__restrict__ pmass2,
+                                                             int nparts, double nodes,
+                                                             const unsigned *__restrict__ ctrl,
+                                                             double *__restrict__ mass) {
+  __shared__ double sm[kThreads];
+  if (ctrl[0] == 0) return;
+  double m = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kThreads) m += pmass2[k];
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *mass = nodes + sm[0];
+}
+
+}  // namespace gnn
+
+// ------------------------------------------------------------------- ABI ---
+
+using namespace gnn;
+using lbm::check_device;
+using lbm::fail;
+using lbm::launch_check;
+
+static int device_cus() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+static inline void *at(void *base, size_t off) { return (uint8_t *)base + off; }
 
 extern "C" size_t gnn_param_count(int n_rounds) {
-  if (n_rounds < 1 || n_rounds > gnn::MAX_ROUNDS) return 0;
-  return gnn::blob_layout(n_rounds).nparam;
+  if (n_rounds < 1 || n_rounds > MAX_ROUNDS) return 0;
+  return blob_layout(n_rounds).nparam;
 }
 extern "C" size_t gnn_blob_len(int n_rounds) {
-  if (n_rounds < 1 || n_rounds > gnn::MAX_ROUNDS) return 0;
-  return gnn::blob_layout(n_rounds).total;
+  if (n_rounds < 1 || n_rounds > MAX_ROUNDS) return 0;
+  return blob_layout(n_rounds).total;
 }
-extern "C" int lbm_step_gnn(const float *, float *, int, int, float, const float *, int,
-                            const lbm_fallback *, void *, size_t, void *) {
-  return fail(LBM_EUNSUPPORTED, "lbm_step_gnn: not built yet");
+
+namespace gnn {
+
+// Launches weight packing, encoder and rounds.  src: populations the
+// collision starts from (post-collision state of the previous step when
+// PULL, else pre-collision); the last round writes dst and the partials.
+int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, int ny,
+                   const float *tau_arr, float tau, const float *params, int R, float *head_out,
+                   void *saved, void *ws, hipStream_t s, int &nparts) {
+  const long long nodes = (long long)batch * nx * ny;
+  const BlobLayout L = blob_layout(R);
+  const FragLayout F = frag_layout(R);
+  const ForwardScratch W = forward_scratch(nodes);
+  if (F.total > kPackBytes) return fail(LBM_EINVAL, "packed weights exceed their scratch");
+  uint8_t *pack = (uint8_t *)at(ws, W.pack);
+  hipLaunchKernelGGL(gnn_prep_kernel, dim3(F.nfrag + F.nbias + 1), dim3(64), 0, s, params, R,
+                     L, F, pack);
+  if (int rc = launch_check("gnn_prep_kernel")) return rc;
+
+  const int cus = device_cus();
+  const bool save = saved != nullptr;
+  SavedLayout S{};
+  if (save) S = saved_layout(nodes, R);
+  auto hbuf = [&](int r) -> uint16_t * {  // node states h_r
+    if (save) return (uint16_t *)at(saved, S.h + (size_t)r * align256((size_t)nodes * HID * 2));
+    return (uint16_t *)at(ws, (r & 1) ? W.hB : W.hA);
+  };
+
+  long long groups = (long long)batch * ny * ((nx + 15) / 16);
+  long long eblocks = (groups + kWaves - 1) / kWaves;
+  int eb = (int)(eblocks < (long long)cus * 8 ? eblocks : (long long)cus * 8);
+  uint16_t *sx = save ? (uint16_t *)at(saved, S.x) : nullptr;
+  uint16_t *se = save ? (uint16_t *)at(saved, S.e1) : nullptr;
+  if (pull) {
+    hipLaunchKernelGGL((gnn_encode_kernel<true, false>), dim3(eb), dim3(kThreads), 0, s, src,
+                       batch, nx, ny, pack, F, hbuf(0), sx, se);
+  } else if (save) {
+    hipLaunchKernelGGL((gnn_encode_kernel<false, true>), dim3(eb), dim3(kThreads), 0, s, src,
+                       batch, nx, ny, pack, F, hbuf(0), sx, se);
+  } else {
+    hipLaunchKernelGGL((gnn_encode_kernel<false, false>), dim3(eb), dim3(kThreads), 0, s, src,
+                       batch, nx, ny, pack, F, hbuf(0), sx, se);
+  }
+  if (int rc = launch_check("gnn_encode_kernel")) return rc;
+
+  long long ntiles = (long long)batch * ((nx + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE);
+  long long cap = (long long)cus * 2;
+  if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
+  int rb = (int)(ntiles < cap ? ntiles : cap);
+  nparts = rb;
+  HeadArgs none{};
+  HeadArgs ha{};
+  ha.src = src;
+  ha.dst = dst;
+  ha.tau_arr = tau_arr;
+  ha.tau = tau;
+  ha.head_out = head_out;
+  ha.save_z = save ? (float *)at(saved, S.z) : nullptr;
+  ha.pmass = (double *)at(ws, W.pmass);
+  ha.pflag = (unsigned *)at(ws, W.pflag);
+  for (int r = 0; r < R; ++r) {
+    const bool head = r == R - 1;
+    uint16_t *hin = hbuf(r);
+    uint16_t *hout = head ? (save ? hbuf(r + 1) : nullptr) : hbuf(r + 1);
+    uint16_t *sag = save ? (uint16_t *)at(saved, S.agg + (size_t)r * align256((size_t)nodes * HID * 2))
+                         : nullptr;
+    if (!head) {
+      if (save)
+        hipLaunchKernelGGL((gnn_round_kernel<false, false, true>), dim3(rb), dim3(kThreads), 0,
+                           s, hin, hout, sag, batch, nx, ny, r, pack, F, none);
+      else
+        hipLaunchKernelGGL((gnn_round_kernel<false, false, false>), dim3(rb), dim3(kThreads), 0,
+                           s, hin, hout, sag, batch, nx, ny, r, pack, F, none);
+    } else if (pull) {
+      hipLaunchKernelGGL((gnn_round_kernel<true, true, false>), dim3(rb), dim3(kThreads), 0, s,
+                         hin, hout, sag, batch, nx, ny, r, pack, F, ha);
+    } else if (save) {
+      hipLaunchKernelGGL((gnn_round_kernel<true, false, true>), dim3(rb), dim3(kThreads), 0, s,
+                         hin, hout, sag, batch, nx, ny, r, pack, F, ha);
+    } else {
+      hipLaunchKernelGGL((gnn_round_kernel<true, false, false>), dim3(rb), dim3(kThreads), 0, s,
+                         hin, hout, sag, batch, nx, ny, r, pack, F, ha);
+    }
+    if (int rc = launch_check("gnn_round_kernel")) return rc;
+  }
+  return LBM_OK;
 }
-extern "C" int gnn_forward(const float *, float *, int, int, int, const float *, const float *,
-                           int, float *, void *, size_t, void *, size_t, void *) {
-  return fail(LBM_EUNSUPPORTED, "gnn_forward: not built yet");
+
+}  // namespace gnn
+
+static int check_gnn_common(const char *who, int batch, int nx, int ny, const float *params,
+                            int R) {
+  if (!params) return fail(LBM_EINVAL, "%s: null parameters", who);
+  if (R < 1 || R > MAX_ROUNDS) return fail(LBM_EINVAL, "%s: n_rounds %d not in [1, %d]", who, R,
+                                           MAX_ROUNDS);
+  if (batch < 1 || !lbm::lattice_ok(nx, ny) || (long long)batch * nx * ny >= (1LL << 31))
+    return fail(LBM_EINVAL, "%s: bad sizes batch %d, %d x %d", who, batch, nx, ny);
+  return LBM_OK;
 }
+
+extern "C" int gnn_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
+                           const float *tau, const float *params, int n_rounds, float *head_out,
+                           void *saved, size_t saved_bytes, void *workspace, size_t ws_bytes,
+                           void *stream) {
+  if (int rc = check_gnn_common("gnn_forward", batch, nx, ny, params, n_rounds)) return rc;
+  if (!g_pre || !g_post || !tau) return fail(LBM_EINVAL, "gnn_forward: null pointer");
+  size_t bytes = (size_t)batch * 9 * nx * ny * sizeof(float);
+  if (lbm::overlap(g_pre, g_post, bytes))
+    return fail(LBM_EINVAL, "gnn_forward: g_pre and g_post overlap");
+  size_t need = forward_workspace_bytes(batch, nx, ny, n_rounds);
+  if (!workspace || ws_bytes < need)
+    return fail(LBM_EWORKSPACE, "gnn_forward: workspace needs %zu bytes", need);
+  const size_t saved_need = gnn::saved_bytes(batch, nx, ny, n_rounds);
+  if (saved && saved_bytes < saved_need)
+    return fail(LBM_EWORKSPACE, "gnn_forward: saved buffer needs %zu bytes", saved_need);
+  if (int rc = check_device()) return rc;
+  int nparts = 0;
+  return launch_forward(false, g_pre, g_post, batch, nx, ny, tau, 0.0f, params, n_rounds,
+                        head_out, saved, workspace, (hipStream_t)stream, nparts);
+}
+
+extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                            const float *params, int n_rounds, const lbm_fallback *fb,
+                            void *workspace, size_t ws_bytes, void *stream) {
+  if (int rc = check_gnn_common("lbm_step_gnn", 1, nx, ny, params, n_rounds)) return rc;
+  if (!g_src || !g_dst) return fail(LBM_EINVAL, "lbm_step_gnn: null pointer");
+  if (!(tau > 0.0f)) return fail(LBM_EINVAL, "lbm_step_gnn: tau must be positive");
+  size_t bytes = (size_t)9 * nx * ny * sizeof(float);
+  if (lbm::overlap(g_src, g_dst, bytes))
+    return fail(LBM_EINVAL, "lbm_step_gnn: source and destination overlap");
+  if (fb && (!fb->flags || !fb->mass))
+    return fail(LBM_EINVAL, "lbm_step_gnn: fallback needs flags and mass pointers");
+  size_t need = step_workspace_bytes(nx, ny, n_rounds);
+  if (!workspace || ws_bytes < need)
+    return fail(LBM_EWORKSPACE, "lbm_step_gnn: workspace needs %zu bytes", need);
+  if (int rc = check_device()) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int nparts = 0;
+  if (int rc = launch_forward(true, g_src, g_dst, 1, nx, ny, nullptr, tau, params, n_rounds,
+                              nullptr, nullptr, workspace, s, nparts))
+    return rc;
+  if (!fb) return LBM_OK;
+  const ForwardScratch W = forward_scratch((long long)nx * ny);
+  double nodes = (double)nx * ny;
+  unsigned *ctrl = (unsigned *)at(workspace, W.ctrl);
+  hipLaunchKernelGGL(gate_decide_kernel, dim3(1), dim3(kThreads), 0, s,
+                     (const double *)at(workspace, W.pmass),
+                     (const unsigned *)at(workspace, W.pflag), nparts, nodes,
+                     fb->drift_threshold, fb->flags, fb->n_fallback, fb->mass, ctrl);
+  if (int rc = launch_check("gate_decide_kernel")) return rc;
+  long long fbn = ((long long)nx * ny + kThreads - 1) / kThreads;
+  int fbb = (int)(fbn < kMaxGnnBlocks ? fbn : kMaxGnnBlocks);
+  double *pm2 = (double *)at(workspace, W.pmass2);
+  hipLaunchKernelGGL(gate_fallback_kernel, dim3(fbb), dim3(kThreads), 0, s, g_src, g_dst, nx, ny,
+                     1.0f / tau, ctrl, pm2);
+  if (int rc = launch_check("gate_fallback_kernel")) return rc;
+  hipLaunchKernelGGL(gate_mass_kernel, dim3(1), dim3(kThreads), 0, s, pm2, fbb, nodes, ctrl,
+                     fb->mass);
+  return launch_check("gate_mass_kernel");
+}
+
 extern "C" int gnn_backward(const float *, const float *, const void *, int, int, int,
                             const float *, const float *, int, float *, void *, size_t, void *) {
   return fail(LBM_EUNSUPPORTED, "gnn_backward: not built yet");

@@ -73,18 +73,30 @@ inline size_t saved_bytes(int batch, int nx, int ny, int R) {
   return saved_layout((long long)batch * nx * ny, R).total;
 }
 
-// Scratch of one forward pass without saved activations: two BF16 node-state
-// buffers (ping-pong), per-block FP64 partials and a few control words.
+// Upper bound on the workgroups of a GNN launch (grids are clamped to it);
+// sizes the per-workgroup partial sums.
+constexpr int kMaxGnnBlocks = 2048;
+
+// Bytes of the packed weight fragments (see gnn_common.hpp); generous bound
+// that holds for every n_rounds <= MAX_ROUNDS.
+constexpr size_t kPackBytes = 512 * 1024;
+
+// Scratch of one forward pass: packed weights, two BF16 node-state buffers
+// (ping-pong), per-workgroup FP64 mass and flag partials of the corrected
+// collision and of the fallback step, and a few control words.
 struct ForwardScratch {
-  size_t hA, hB, partials, ctrl, total;
+  size_t pack, hA, hB, pmass, pflag, pmass2, ctrl, total;
 };
 
 inline ForwardScratch forward_scratch(long long nodes) {
   ForwardScratch F{};
   size_t n = (size_t)nodes, o = 0;
+  F.pack = o; o += kPackBytes;
   F.hA = o; o += align256(n * HID * 2);
   F.hB = o; o += align256(n * HID * 2);
-  F.partials = o; o += align256(1024 * 8 * sizeof(double));
+  F.pmass = o; o += align256(kMaxGnnBlocks * sizeof(double));
+  F.pflag = o; o += align256(kMaxGnnBlocks * sizeof(unsigned));
+  F.pmass2 = o; o += align256(kMaxGnnBlocks * sizeof(double));
   F.ctrl = o; o += 256;
   F.total = o;
   return F;

@@ -103,6 +103,17 @@ __device__ __forceinline__ void node_moments(const T (&g)[9], T &drho, T &rho, T
   uu = u * u + v * v;
 }
 
+// BGK collision of one node in shifted variables (Eq. 1 with the
+// equilibrium of Eq. 2).  g[] holds the pre-collision populations (already
+// streamed) and is overwritten by the post-collision ones; omega = 1 / tau.
+template <typename T>
+__device__ __forceinline__ void bgk_collide(T (&g)[9], T omega) {
+  T drho, rho, u, v, uu;
+  node_moments(g, drho, rho, u, v, uu);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = g[i] + omega * (geq_shifted<T>(i, drho, rho, u, v, uu) - g[i]);
+}
+
 // True if the byte ranges [a, a + bytes) and [b, b + bytes) intersect.
 inline bool overlap(const void *a, const void *b, size_t bytes) {
   const char *p = (const char *)a, *q = (const char *)b;

@@ -33,16 +33,6 @@ __global__ void init_kernel(T *__restrict__ g, int nx, int ny, const T *__restri
 
 // ------------------------------------------------------------ BGK, fused ---
 
-// Collision of one node in shifted variables.  g[] holds the pre-collision
-// populations (already streamed) and is overwritten by the post-collision ones.
-template <typename T>
-__device__ __forceinline__ void bgk_collide(T (&g)[9], T omega) {
-  T drho, rho, u, v, uu;
-  node_moments(g, drho, rho, u, v, uu);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = g[i] + omega * (geq_shifted<T>(i, drho, rho, u, v, uu) - g[i]);
-}
-
 constexpr int kBgkThreads = 256;
 
 // One thread per node.  The grid is one-dimensional: block b covers

@@ -1,0 +1,270 @@
+"""GPU parity of the GNN-corrected collision (paper: Methodology, GNN
+enhancement and its integration with the LBM, Eq. 3) against the CPU oracle.
+
+The library computes the network in BF16 with FP32 accumulation.  It is
+compared with the oracle in two modes:
+  mode 0  FP64 throughout: the spec bar (corrected populations within
+          1e-3 relative at the inference workload's correction scale
+          s_delta = 1e-4) and a bound on the correction itself;
+  mode 1  FP64 arithmetic with BF16 rounding at the points where the kernel
+          stores BF16 (weights, features, activations, summed messages):
+          head outputs agree to summation-order effects only.
+Layouts: the library stores [.., ny, 9, nx]; the oracle [.., 9, ny, nx]
+(inputs.planes_to_rows / rows_to_planes, a transpose).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_14494_amd import gnn, inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+R = 2
+
+
+def _w(orc):
+    return orc.lattice()[2][:, None, None]
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _forward(g_planes, taus, blob, want_z=True):
+    """Library forward of shifted pre-collision populations [B, 9, ny, nx];
+    returns the shifted post-collision populations in the same order (float64)
+    and the head outputs z [B, ny, nx, 10]."""
+    out, z = gnn.gnn_forward(_dev(inputs.planes_to_rows(g_planes)), _dev(taus), _dev(blob), R,
+                             want_z=want_z)
+    torch.cuda.synchronize()
+    g_post = inputs.rows_to_planes(out.double().cpu().numpy())
+    return g_post, (z.double().cpu().numpy() if want_z else None)
+
+
+def _bgk_planes(orc, f, taus):
+    return np.stack([orc.collide_bgk(f[b], float(taus[b])) for b in range(f.shape[0])])
+
+
+@pytest.mark.parametrize("B,ny,nx", [(1, 1, 1), (1, 3, 5), (2, 8, 12), (1, 16, 16),
+                                     (1, 17, 33), (1, 40, 24), (3, 20, 37)])
+def test_forward_matches_oracle_at_inference_scale(orc, B, ny, nx):
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=1000 * B + 10 * ny + nx)
+    taus = np.float32(0.6 + 0.07 * np.arange(B))
+    blob = inputs.gnn_blob(0, R, s_delta=1e-4)
+    got, z = _forward(g, taus, blob)
+    f = g.astype(np.float64) + _w(orc)
+    ref, zref = orc.gnn_collide(f, taus.astype(np.float64), blob.astype(np.float64), R, mode=0,
+                                want_z=True)
+    got_f = got + _w(orc)
+    rel = _rel(got_f, ref)
+    bgk = _bgk_planes(orc, f, taus.astype(np.float64))
+    rel_corr = _rel(got_f - bgk, ref - bgk)
+    print(f"f* rel-L2 {rel:.2e}; correction rel-L2 {rel_corr:.2e}; z rel {_rel(z, zref):.2e}")
+    assert rel <= 1e-3
+    assert rel_corr <= 5e-2
+    assert np.isfinite(got).all()
+
+
+@pytest.mark.parametrize("B,ny,nx", [(1, 5, 7), (2, 16, 16), (1, 19, 35)])
+def test_head_matches_bf16_emulating_oracle(orc, B, ny, nx):
+    """s_delta = 1 so that the correction is as large as the populations."""
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=7 * nx + ny)
+    taus = np.float32(np.full(B, 0.8))
+    blob = inputs.gnn_blob(3, R, s_delta=1.0)
+    got, z = _forward(g, taus, blob)
+    f = g.astype(np.float64) + _w(orc)
+    ref1, z1 = orc.gnn_collide(f, taus.astype(np.float64), blob.astype(np.float64), R, mode=1,
+                               want_z=True)
+    rz, rf = _rel(z, z1), _rel(got + _w(orc), ref1)
+    print(f"vs BF16-emulating oracle: z rel-L2 {rz:.2e}, f* rel-L2 {rf:.2e}")
+    assert rz <= 2e-3
+    assert rf <= 2e-3
+
+
+def test_step_gnn_pulls_then_collides(orc):
+    ny, nx = 24, 40
+    post = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=5)
+    blob = inputs.gnn_blob(1, R, s_delta=1e-4)
+    tau = np.float32(0.7)
+    dst = torch.full((ny, 9, nx), float("nan"), device="cuda")
+    gnn.lbm_step_gnn(_dev(inputs.planes_to_rows(post)), dst, float(tau), _dev(blob), R)
+    torch.cuda.synchronize()
+    got = inputs.rows_to_planes(dst.double().cpu().numpy()) + _w(orc)
+    fpre = orc.stream(post.astype(np.float64) + _w(orc))
+    ref = orc.gnn_collide(fpre, float(tau), blob.astype(np.float64), R, mode=0)
+    assert np.isfinite(got).all()
+    assert _rel(got, ref) <= 1e-3
+    bgk = orc.collide_bgk(fpre, float(tau))
+    assert _rel(got - bgk, ref - bgk) <= 5e-2
+
+
+def _zero_head(blob):
+    off = inputs.blob_offsets(R)
+    b = blob.copy()
+    o, shp = off["Wh"]
+    b[o:o + int(np.prod(shp))] = 0
+    o, shp = off["bh"]
+    b[o:o + int(np.prod(shp))] = 0
+    return b
+
+
+@pytest.mark.parametrize("ny,nx", [(7, 9), (33, 48)])
+def test_zero_head_step_equals_bgk_step(ny, nx):
+    """W_h = 0, b_h = 0 gives tau_adj = 1 and delta f = 0: the corrected
+    step must reproduce the plain BGK step value for value."""
+    post = _dev(inputs.planes_to_rows(inputs.random_shifted_state((9, ny, nx), 4e-3, seed=9)))
+    blob = _dev(_zero_head(inputs.gnn_blob(2, R, s_delta=1.0)))
+    a = torch.empty_like(post)
+    b = torch.empty_like(post)
+    gnn.lbm_step_gnn(post, a, 0.63, blob, R)
+    lbm.lbm_step_bgk(post, b, 0.63)
+    assert torch.equal(a, b)
+
+
+def test_batch_lattices_are_independent(orc):
+    """Each lattice of a batch is its own periodic domain with its own tau."""
+    B, ny, nx = 3, 12, 20
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=77)
+    taus = np.float32([0.55, 0.8, 1.3])
+    blob = inputs.gnn_blob(4, R, s_delta=1e-2)
+    got, _ = _forward(g, taus, blob, want_z=False)
+    for b in range(B):
+        one, _ = _forward(g[b:b + 1], taus[b:b + 1], blob, want_z=False)
+        assert np.array_equal(one[0], got[b])
+
+
+def test_translation_equivariance_and_determinism():
+    ny, nx = 40, 56
+    post = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=12)
+    blob = _dev(inputs.gnn_blob(5, R, s_delta=1.0))
+    dst = torch.empty((ny, 9, nx), device="cuda")
+    gnn.lbm_step_gnn(_dev(inputs.planes_to_rows(post)), dst, 0.7, blob, R)
+    again = torch.empty_like(dst)
+    gnn.lbm_step_gnn(_dev(inputs.planes_to_rows(post)), again, 0.7, blob, R)
+    assert torch.equal(dst, again)
+    sy, sx = 5, 11                                     # not multiples of the 16-node tile
+    shifted = np.roll(post, (sy, sx), axis=(1, 2))
+    dst2 = torch.empty_like(dst)
+    gnn.lbm_step_gnn(_dev(inputs.planes_to_rows(shifted)), dst2, 0.7, blob, R)
+    assert torch.equal(torch.roll(dst, (sy, sx), dims=(0, 2)), dst2)
+
+
+def test_receptive_field_is_three_nodes():
+    """One streaming step plus two rounds: a change at one source node can
+    only reach destination nodes within Chebyshev distance 3."""
+    ny, nx = 32, 32
+    post = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=13)
+    blob = _dev(inputs.gnn_blob(6, R, s_delta=1.0))
+    a = torch.empty((ny, 9, nx), device="cuda")
+    gnn.lbm_step_gnn(_dev(inputs.planes_to_rows(post)), a, 0.7, blob, R)
+    pert = post.copy()
+    pert[:, 16, 16] += 1e-3
+    b = torch.empty_like(a)
+    gnn.lbm_step_gnn(_dev(inputs.planes_to_rows(pert)), b, 0.7, blob, R)
+    diff = (a != b).any(dim=1).cpu().numpy()          # [ny, nx]
+    ys, xs = np.nonzero(diff)
+    assert diff[16, 16]
+    assert np.abs(ys - 16).max() <= 3 and np.abs(xs - 16).max() <= 3
+    assert diff[13:20, 13:20].sum() > 30              # the ball is actually reached
+
+
+# --------------------------------------------------------------- fallback ---
+
+def _gate_case(orc, blob, thr, poison=False):
+    ny, nx = 20, 28
+    post = inputs.random_shifted_state((9, ny, nx), 3e-3, seed=31)
+    if poison:
+        post[4, 3, 5] = np.nan
+    src = _dev(inputs.planes_to_rows(post))
+    w = _w(orc)
+    mass0 = float((post.astype(np.float64) + w).sum()) if not poison else float(ny * nx)
+    fb = gnn.Fallback(mass0, thr)
+    dst = torch.empty_like(src)
+    gnn.lbm_step_gnn(src, dst, 0.7, _dev(blob), R, fallback=fb)
+    ref = torch.empty_like(src)
+    lbm.lbm_step_bgk(src, ref, 0.7)
+    torch.cuda.synchronize()
+    return post, dst, ref, fb, mass0
+
+
+def test_fallback_on_negative_populations(orc):
+    blob = inputs.gnn_blob(7, R, s_delta=1.0)
+    off = inputs.blob_offsets(R)
+    o, _ = off["bh"]
+    blob[o + 1:o + 10] = np.float32([50, -50, 0, 0, 0, 0, 0, 0, 0])  # delta f far beyond w
+    post, dst, ref, fb, _ = _gate_case(orc, blob, 1e-6)
+    assert int(fb.flags.item()) & 1
+    assert int(fb.n_fallback.item()) == 1
+    assert torch.equal(dst, ref)
+    fpre = orc.stream(post.astype(np.float64) + _w(orc))
+    _, oflags, omass = orc.gnn_collide_gated(fpre, 0.7, blob.astype(np.float64), 1e-6,
+                                             float(fpre.sum()), R)
+    assert oflags & 1
+    assert abs(fb.mass.item() - omass) / omass < 1e-9
+
+
+def test_fallback_on_drift_threshold(orc):
+    blob = inputs.gnn_blob(8, R, s_delta=1e-4)
+    _, dst, ref, fb, _ = _gate_case(orc, blob, -1.0)
+    assert int(fb.flags.item()) == 2
+    assert int(fb.n_fallback.item()) == 1
+    assert torch.equal(dst, ref)
+
+
+def test_no_fallback_keeps_corrected_step_and_updates_mass(orc):
+    blob = inputs.gnn_blob(9, R, s_delta=1e-4)
+    post, dst, ref, fb, mass0 = _gate_case(orc, blob, 1e-6)
+    assert int(fb.flags.item()) == 0 and int(fb.n_fallback.item()) == 0
+    assert not torch.equal(dst, ref)
+    got = inputs.rows_to_planes(dst.double().cpu().numpy()) + _w(orc)
+    assert abs(fb.mass.item() - got.sum()) / got.sum() < 1e-12
+    # projection: the corrected collision conserves mass to FP32 roundoff
+    assert abs(fb.mass.item() - mass0) / mass0 < 1e-6
+
+
+def test_fallback_on_non_finite_source(orc):
+    blob = inputs.gnn_blob(10, R, s_delta=1e-4)
+    _, dst, ref, fb, _ = _gate_case(orc, blob, 1e-6, poison=True)
+    assert int(fb.flags.item()) & 1
+    assert torch.equal(torch.nan_to_num(dst, nan=7.0), torch.nan_to_num(ref, nan=7.0))
+
+
+# ------------------------------------------------------ full-size sample ---
+
+def test_inference_workload_2048_sampled_nodes(orc):
+    """The 2048^2 inference workload in the benchmark's launch configuration:
+    100 BGK steps of Taylor-Green (Re = 1000, u0 = 0.04), then one corrected
+    step; 256 random nodes checked against the oracle evaluated on their own
+    neighbourhoods."""
+    n, u0 = 2048, 0.04
+    _, tau = inputs.tgv_params(n, u0, 1000.0)
+    tau = float(np.float32(tau))
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
+    blob = inputs.gnn_blob(0, R, s_delta=1e-4, u0=u0)
+    lat = gnn.GnnLattice(n, n, _dev(blob), R).init(rho, ux, uy)
+    lat.step_bgk(tau, 100)
+    src = lat.a.clone()
+    lat.step_gnn(tau, 1)
+    torch.cuda.synchronize()
+    assert int(lat.n_fallback.item()) == 0
+    post = inputs.rows_to_planes(src.double().cpu().numpy()) + _w(orc)
+    fpre = orc.stream(post)
+    rng = np.random.default_rng(2048)
+    nodes = rng.integers(0, n * n, 256)
+    nodes[:4] = [0, n - 1, n * n - 1, n * (n - 1)]    # corners: wrap in x and y
+    ref, zref = orc.gnn_collide_nodes(fpre, tau, blob.astype(np.float64), nodes, R, mode=0)
+    out = lat.a.double()
+    ys, xs = nodes // n, nodes % n
+    got = out[torch.as_tensor(ys), :, torch.as_tensor(xs)].cpu().numpy() + _w(orc)[:, 0, 0]
+    rel = _rel(got, ref)
+    bgk = np.stack([orc.collide_bgk(fpre[:, y:y + 1, x:x + 1], tau)[:, 0, 0]
+                    for y, x in zip(ys, xs)])
+    rel_c = _rel(got - bgk, ref - bgk)
+    print(f"2048^2 sampled: f* rel-L2 {rel:.2e}, correction rel-L2 {rel_c:.2e}")
+    assert rel <= 1e-3
+    assert rel_c <= 5e-2
