@@ -63,6 +63,11 @@ __device__ __forceinline__ u32x4 frag_from_acc(f32x4 lo, f32x4 hi) {
   return r;
 }
 
+// BF16 bits of a small integer in {-1, 0, 1}.
+__host__ __device__ constexpr uint32_t bf16_unit(int v) {
+  return v == 0 ? 0u : (v > 0 ? 0x3f80u : 0xbf80u);
+}
+
 // GELU, tanh form: 0.5 x (1 + tanh(k0 (x + k1 x^3))) = x / (1 + 2^t) with
 // t = -2 k0 log2(e) (x + k1 x^3).  One hardware exp2 and one reciprocal.
 constexpr float kGeluA = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
@@ -151,6 +156,17 @@ __device__ __forceinline__ u32x4 load_frag(const u32x4 *__restrict__ frags, int 
 }
 __device__ __forceinline__ f32x4 load_bias(const f32x4 *__restrict__ bias, int b, int lane) {
   return bias[(size_t)b * 64 + lane];
+}
+
+// Packs the FP32 blob into `pack` (frag_layout(R).total bytes) on stream s.
+int launch_prep(const float *params, int R, uint8_t *pack, hipStream_t s);
+
+// Makes the LDS writes of this wave visible to all of its lanes before the
+// reads that follow (LDS staging private to one wave).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 }  // namespace gnn

@@ -259,11 +259,6 @@ constexpr int TILE = 16;            // receivers per tile edge
 constexpr int HALO = TILE + 2;      // node states of the tile and its 1-node ring
 constexpr int HNODES = HALO * HALO;
 
-// BF16 bits of a small integer in {-1, 0, 1}.
-__host__ __device__ constexpr uint32_t bf16_unit(int v) {
-  return v == 0 ? 0u : (v > 0 ? 0x3f80u : 0xbf80u);
-}
-
 // Node state fragment (k-step s, lane group q) of LDS node ln.  The 8
 // 16-byte chunks of a node are XOR-swizzled with the node index so that
 // 16 lanes reading the same chunk of 16 consecutive nodes spread over banks.
@@ -634,6 +629,15 @@ extern "C" size_t gnn_blob_len(int n_rounds) {
 
 namespace gnn {
 
+int launch_prep(const float *params, int R, uint8_t *pack, hipStream_t s) {
+  const BlobLayout L = blob_layout(R);
+  const FragLayout F = frag_layout(R);
+  if (F.total > kPackBytes) return fail(LBM_EINVAL, "packed weights exceed their scratch");
+  hipLaunchKernelGGL(gnn_prep_kernel, dim3(F.nfrag + F.nbias + 1), dim3(64), 0, s, params, R, L,
+                     F, pack);
+  return launch_check("gnn_prep_kernel");
+}
+
 // Launches weight packing, encoder and rounds.  src: populations the
 // collision starts from (post-collision state of the previous step when
 // PULL, else pre-collision); the last round writes dst and the partials.
@@ -641,14 +645,10 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
                    const float *tau_arr, float tau, const float *params, int R, float *head_out,
                    void *saved, void *ws, hipStream_t s, int &nparts) {
   const long long nodes = (long long)batch * nx * ny;
-  const BlobLayout L = blob_layout(R);
   const FragLayout F = frag_layout(R);
   const ForwardScratch W = forward_scratch(nodes);
-  if (F.total > kPackBytes) return fail(LBM_EINVAL, "packed weights exceed their scratch");
   uint8_t *pack = (uint8_t *)at(ws, W.pack);
-  hipLaunchKernelGGL(gnn_prep_kernel, dim3(F.nfrag + F.nbias + 1), dim3(64), 0, s, params, R,
-                     L, F, pack);
-  if (int rc = launch_check("gnn_prep_kernel")) return rc;
+  if (int rc = launch_prep(params, R, pack, s)) return rc;
 
   const int cus = device_cus();
   const bool save = saved != nullptr;
@@ -790,17 +790,4 @@ extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, fl
   hipLaunchKernelGGL(gate_mass_kernel, dim3(1), dim3(kThreads), 0, s, pm2, fbb, nodes, ctrl,
                      fb->mass);
   return launch_check("gate_mass_kernel");
-}
-
-extern "C" int gnn_backward(const float *, const float *, const void *, int, int, int,
-                            const float *, const float *, int, float *, void *, size_t, void *) {
-  return fail(LBM_EUNSUPPORTED, "gnn_backward: not built yet");
-}
-extern "C" int gnn_mse(const float *, const float *, int, int, int, double, double *, float *,
-                       void *, size_t, void *) {
-  return fail(LBM_EUNSUPPORTED, "gnn_mse: not built yet");
-}
-extern "C" int gnn_adam(float *, const float *, float *, float *, size_t, float, float, float,
-                        float, int, void *) {
-  return fail(LBM_EUNSUPPORTED, "gnn_adam: not built yet");
 }

@@ -111,21 +111,26 @@ inline size_t step_workspace_bytes(int nx, int ny, int R) {
   return forward_workspace_bytes(1, nx, ny, R);
 }
 
-// Backward scratch: FP32 node-state gradients (two buffers), FP32 summed
-// message gradients, and per-block FP32 parameter-gradient partials.
-constexpr int kGradBlocks = 256;
+// Backward scratch: packed weights, two FP32 node-gradient buffers
+// (ping-pong over the rounds), FP32 gradients of the summed messages, BF16
+// per-edge gradients of the edge-layer pre-activations [N][8][64], and one
+// FP32 partial parameter gradient per wave of the fixed backward grid.
+constexpr int kBwdBlocks = 256;
+constexpr int kBwdWaves = kBwdBlocks * 4;
 struct BackwardScratch {
-  size_t dh, dhp, dagg, part, total;
+  size_t pack, dhA, dhB, dagg, dq, part, total;
 };
 
 inline BackwardScratch backward_scratch(long long nodes, int R) {
   BackwardScratch B{};
   size_t n = (size_t)nodes, o = 0;
   size_t np = blob_layout(R).nparam;
-  B.dh = o; o += align256(n * HID * 4);
-  B.dhp = o; o += align256(n * HID * 4);
+  B.pack = o; o += kPackBytes;
+  B.dhA = o; o += align256(n * HID * 4);
+  B.dhB = o; o += align256(n * HID * 4);
   B.dagg = o; o += align256(n * HID * 4);
-  B.part = o; o += align256((size_t)kGradBlocks * np * 4);
+  B.dq = o; o += align256(n * 8 * HID * 2);
+  B.part = o; o += align256((size_t)kBwdWaves * np * 4);
   B.total = o;
   return B;
 }

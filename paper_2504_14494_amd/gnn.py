@@ -16,7 +16,8 @@ from ._lib import LbmFallback, check
 from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
-           "Fallback", "GnnLattice"]
+           "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
+           "GnnMse"]
 
 
 def gnn_param_count(rounds: int = 2) -> int:
@@ -157,3 +158,110 @@ class GnnLattice(Lattice):
             self.a, self.b = self.b, self.a
             self.steps += 1
         return self
+
+
+def backward_ws_bytes(batch: int, nx: int, ny: int, rounds: int = 2) -> int:
+    return int(_lib.load().lbm_workspace_bytes(_lib.LBM_WS_GNN_BACKWARD, batch, nx, ny, rounds))
+
+
+def gnn_backward(dL_dgpost: torch.Tensor, g_pre: torch.Tensor, saved: torch.Tensor,
+                 tau: torch.Tensor, blob: torch.Tensor, rounds: int = 2,
+                 grad: torch.Tensor = None, ws: Workspace = None) -> torch.Tensor:
+    """dL/dparams (FP32, [gnn_param_count]) of the gnn_forward call that
+    filled `saved` (same g_pre, tau, blob), given dL/dg_post."""
+    if g_pre.dim() == 3:
+        g_pre, dL_dgpost = g_pre.unsqueeze(0), dL_dgpost.unsqueeze(0)
+    _need(g_pre, torch.float32, "g_pre")
+    _need(dL_dgpost, torch.float32, "dL_dgpost")
+    _need(saved, torch.uint8, "saved")
+    B, nx, ny = _batch_dims(g_pre)
+    if dL_dgpost.shape != g_pre.shape:
+        raise ValueError("dL_dgpost must match g_pre")
+    _check_blob(blob, rounds)
+    if grad is None:
+        grad = torch.empty(gnn_param_count(rounds), dtype=torch.float32, device=g_pre.device)
+    _need(grad, torch.float32, "grad")
+    buf = (ws or _ws_bwd).get(backward_ws_bytes(B, nx, ny, rounds))
+    rc = _lib.load().gnn_backward(_ptr(dL_dgpost), _ptr(g_pre), _ptr(saved), B, nx, ny,
+                                  _ptr(tau), _ptr(blob), rounds, _ptr(grad), _ptr(buf),
+                                  buf.numel(), _stream())
+    check(rc, "gnn_backward")
+    return grad
+
+
+_ws_bwd = Workspace()
+
+
+def gnn_mse(a: torch.Tensor, b: torch.Tensor, scale: float = 1.0, want_grad: bool = True,
+            ws: Workspace = None):
+    """Eq. 4 over all nodes of a batch: scale / N * sum (a - b)^2, N = number
+    of nodes.  Returns (loss as a device float64 [1], dloss/da or None)."""
+    _need(a, torch.float32, "a")
+    _need(b, torch.float32, "b")
+    if a.shape != b.shape or a.numel() % 9:
+        raise ValueError("a and b must be populations of the same shape")
+    nodes = a.numel() // 9
+    loss = torch.empty(1, dtype=torch.float64, device=a.device)
+    grad = torch.empty_like(a) if want_grad else None
+    L = _lib.load()
+    buf = (ws or _ws).get(L.lbm_workspace_bytes(_lib.LBM_WS_MSE, 1, nodes, 1, 0))
+    rc = L.gnn_mse(_ptr(a), _ptr(b), 1, nodes, 1, float(scale), _ptr(loss), _ptr(grad),
+                   _ptr(buf), buf.numel(), _stream())
+    check(rc, "gnn_mse")
+    return loss, grad
+
+
+def gnn_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+             step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8):
+    """One in-place Adam step on the first grad.numel() entries of params."""
+    n = grad.numel()
+    for t, nm in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, nm)
+    if params.numel() < n or m.numel() < n or v.numel() < n:
+        raise ValueError("params, m and v must hold at least grad.numel() values")
+    rc = _lib.load().gnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, float(lr),
+                              float(beta1), float(beta2), float(eps), int(step), _stream())
+    check(rc, "gnn_adam")
+
+
+class GnnCollide(torch.autograd.Function):
+    """torch.autograd face of the corrected collision: forward = gnn_forward
+    (activations saved), backward = gnn_backward (gradient with respect to the
+    parameter blob only; populations and tau are data)."""
+
+    @staticmethod
+    def forward(ctx, blob, g_pre, tau, rounds):
+        B, nx, ny = _batch_dims(g_pre)
+        saved = torch.empty(saved_bytes(B, nx, ny, rounds), dtype=torch.uint8,
+                            device=g_pre.device)
+        out, _ = gnn_forward(g_pre, tau, blob.detach(), rounds, saved=saved)
+        ctx.save_for_backward(blob, g_pre, tau)
+        ctx.saved_acts = saved
+        ctx.rounds = rounds
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        blob, g_pre, tau = ctx.saved_tensors
+        gp = gnn_backward(grad_out.contiguous(), g_pre, ctx.saved_acts, tau, blob.detach(),
+                          ctx.rounds)
+        full = torch.zeros_like(blob)
+        full[:gp.numel()] = gp
+        ctx.saved_acts = None
+        return full, None, None, None
+
+
+class GnnMse(torch.autograd.Function):
+    """Eq. 4 (scaled) with its gradient from the gnn_mse kernel."""
+
+    @staticmethod
+    def forward(ctx, a, b, scale):
+        loss, grad = gnn_mse(a.detach(), b, scale, want_grad=True)
+        ctx.save_for_backward(grad)
+        return loss.to(torch.float32).reshape(())
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return grad * gout, None, None

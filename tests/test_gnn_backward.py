@@ -1,0 +1,147 @@
+"""GPU parity of the hand-written backward pass, the Eq. 4 loss and the Adam
+update (paper: Training Methodology) against the CPU oracle.
+
+The oracle's reference gradient is the exact derivative of its forward,
+itself pinned by central differences and by torch autograd on the CPU.  It
+is evaluated on the BF16-rounded forward (mode 1) with the rounding
+differentiated as the identity, the same convention as the kernels.  The
+kernels also round the backward's MFMA operands (gradient rows, per-edge
+gradients) to BF16, so the bar is 2e-2 relative L2 per parameter tensor.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_14494_amd import gnn, inputs
+
+pytestmark = pytest.mark.gpu
+
+R = 2
+
+
+def _w(orc):
+    return orc.lattice()[2][:, None, None]
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _gpu_grad(g_planes, G_planes, taus, blob):
+    g = _dev(inputs.planes_to_rows(g_planes))
+    G = _dev(inputs.planes_to_rows(G_planes))
+    B, _, ny, nx = g_planes.shape
+    saved = torch.empty(gnn.saved_bytes(B, nx, ny, R), dtype=torch.uint8, device="cuda")
+    t, b = _dev(taus), _dev(blob)
+    gnn.gnn_forward(g, t, b, R, saved=saved)
+    grad = gnn.gnn_backward(G, g, saved, t, b, R)
+    torch.cuda.synchronize()
+    return grad.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("B,ny,nx,sd", [(2, 12, 20, 1.0), (1, 17, 19, 1e-2), (1, 3, 4, 1.0)])
+def test_backward_matches_oracle_gradient(orc, B, ny, nx, sd):
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=100 + nx)
+    G = inputs.random_shifted_state((B, 9, ny, nx), 1.0, seed=200 + nx)
+    taus = np.float32(0.6 + 0.1 * np.arange(B))
+    blob = inputs.gnn_blob(11, R, s_delta=sd)
+    got = _gpu_grad(g, G, taus, blob)
+    ref = orc.gnn_backward(g.astype(np.float64) + _w(orc)[None], G.astype(np.float64),
+                           taus.astype(np.float64), blob.astype(np.float64), R, mode=1)
+    worst = {}
+    for name, (o, shp) in inputs.blob_offsets(R).items():
+        if name in ("mu", "sigma", "s_delta"):
+            continue
+        k = int(np.prod(shp))
+        worst[name] = _rel(got[o:o + k], ref[o:o + k])
+    print("per-tensor rel-L2:", {k: f"{v:.1e}" for k, v in worst.items()})
+    assert max(worst.values()) <= 2e-2, worst
+    assert _rel(got, ref) <= 1e-2
+
+
+def test_backward_is_deterministic():
+    B, ny, nx = 2, 20, 24
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=3)
+    G = inputs.random_shifted_state((B, 9, ny, nx), 1.0, seed=4)
+    taus = np.float32([0.7, 0.9])
+    blob = inputs.gnn_blob(12, R, s_delta=1.0)
+    a = _gpu_grad(g, G, taus, blob)
+    b = _gpu_grad(g, G, taus, blob)
+    assert np.array_equal(a, b)
+
+
+def test_mse_is_eq4(orc):
+    a = inputs.random_shifted_state((3, 10, 9, 14), 4e-3, seed=5)
+    b = inputs.random_shifted_state((3, 10, 9, 14), 4e-3, seed=6)
+    loss, grad = gnn.gnn_mse(_dev(a), _dev(b), scale=2.5)
+    nodes = a.size // 9
+    ref = 2.5 * orc.mse(inputs.rows_to_planes(a.astype(np.float64)),
+                        inputs.rows_to_planes(b.astype(np.float64)))
+    assert abs(loss.item() - ref) / ref < 1e-6
+    gref = 2.0 * 2.5 / nodes * (a.astype(np.float64) - b)
+    assert np.abs(grad.double().cpu().numpy() - gref).max() <= 1e-6 * np.abs(gref).max()
+
+
+def test_adam_matches_oracle(orc):
+    rng = np.random.default_rng(7)
+    n = 5000
+    p = rng.standard_normal(n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    P, M, V = _dev(p), _dev(m), _dev(v)
+    pr, mr, vr = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 4):
+        g = rng.standard_normal(n).astype(np.float32)
+        gnn.gnn_adam(P, _dev(g), M, V, step, lr=1e-3)
+        orc.adam(pr, g.astype(np.float64), mr, vr, 1e-3, 0.9, 0.999, 1e-8, step)
+    torch.cuda.synchronize()
+    assert np.abs(P.double().cpu().numpy() - pr).max() <= 1e-6
+    assert _rel(M.double().cpu().numpy(), mr) <= 1e-6
+
+
+def test_autograd_function_routes_through_the_kernels():
+    B, ny, nx = 2, 16, 16
+    g = _dev(inputs.planes_to_rows(inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=8)))
+    tgt = _dev(inputs.planes_to_rows(inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=9)))
+    taus = _dev(np.float32([0.7, 0.8]))
+    blob = _dev(inputs.gnn_blob(13, R, s_delta=1e-2)).requires_grad_(True)
+    out = gnn.GnnCollide.apply(blob, g, taus, R)
+    loss = gnn.GnnMse.apply(out, tgt, 1e6)
+    loss.backward()
+    # the same gradient directly from the entry points
+    saved = torch.empty(gnn.saved_bytes(B, nx, ny, R), dtype=torch.uint8, device="cuda")
+    out2, _ = gnn.gnn_forward(g, taus, blob.detach(), R, saved=saved)
+    assert torch.equal(out.detach(), out2)
+    _, dl = gnn.gnn_mse(out2, tgt, 1e6)
+    direct = gnn.gnn_backward(dl, g, saved, taus, blob.detach(), R)
+    npar = gnn.gnn_param_count(R)
+    assert torch.equal(blob.grad[:npar], direct)
+    assert torch.count_nonzero(blob.grad[npar:]) == 0
+
+
+def test_adam_steps_lower_the_loss_on_a_fixed_batch():
+    B, ny, nx = 4, 16, 16
+    g = _dev(inputs.planes_to_rows(inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=10)))
+    taus = _dev(np.float32([0.6, 0.7, 0.8, 0.9]))
+    b0 = inputs.gnn_blob(14, R, s_delta=1e-3)
+    b1 = b0.copy()
+    o, _ = inputs.blob_offsets(R)["bh"]
+    b1[o:o + 10] += 0.5                                  # a reachable target
+    blob = _dev(b0)
+    tgt = gnn.gnn_forward(g, taus, _dev(b1), R)[0]
+    m = torch.zeros(gnn.gnn_param_count(R), device="cuda")
+    v = torch.zeros_like(m)
+    losses = []
+    for step in range(1, 41):
+        saved = torch.empty(gnn.saved_bytes(B, nx, ny, R), dtype=torch.uint8, device="cuda")
+        out, _ = gnn.gnn_forward(g, taus, blob, R, saved=saved)
+        loss, dl = gnn.gnn_mse(out, tgt, 1e8)
+        losses.append(loss.item())
+        grad = gnn.gnn_backward(dl, g, saved, taus, blob, R)
+        gnn.gnn_adam(blob, grad, m, v, step, lr=1e-3)
+    print("loss:", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.75 * losses[0]

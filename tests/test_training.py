@@ -1,0 +1,69 @@
+"""Training on data the plain method generates (paper: Training
+Methodology): the pair generator against the oracle, bitwise checkpoint
+resume, and the gain of the trained collision over plain BGK on held-out
+Taylor-Green flows.  Training itself has no unique answer; its acceptance is
+the gain (parity unpinned beyond the pieces: forward, backward, loss, Adam
+and the data pairs, each checked against the oracle)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_14494_amd import inputs, train
+
+pytestmark = pytest.mark.gpu
+
+
+def test_pairs_match_oracle_generated_pairs(orc):
+    cfg = train.DataConfig(n_fine=32, factor=4, runs=1, snaps=2, coarse_steps=6, seed=3)
+    u0, re, ph = 0.05, 1500.0, (0.3, 0.7)
+    X, Y, tau_c = train.run_pairs(u0, re, ph, cfg)
+    tau_f, tc = train.taus(u0, re, 32, 4)
+    assert tc == tau_c
+    rho, ux, uy = inputs.tgv_velocity(32, 32, u0, x0=ph[0] * 32, y0=ph[1] * 32)
+    f0 = orc.init_equilibrium(rho, ux, uy)
+    w = orc.lattice()[2][:, None, None]
+    for k, m in enumerate(cfg.snapshot_steps()):
+        # the library streams post-collision states: after 4m of its steps the
+        # next pre-collision state is the oracle's state after 4m + 1 steps
+        f = orc.bgk_run(f0, tau_f, 4 * m + 1)
+        xin = orc.restrict(f, 4, tau_f, tau_c)
+        ftgt = orc.bgk_run(f, tau_f, 4)
+        yt = orc.restrict(ftgt, 4, tau_f, tau_c, unstream_=True)
+        gx = inputs.rows_to_planes(X[k].double().cpu().numpy()) + w
+        gy = inputs.rows_to_planes(Y[k].double().cpu().numpy()) + w
+        assert np.abs(gx - xin).max() < 1e-7
+        assert np.abs(gy - yt).max() < 1e-7
+
+
+def _small_cfg():
+    return train.DataConfig(n_fine=128, factor=4, runs=8, snaps=8, coarse_steps=400, seed=11)
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    cfg = dataclasses.replace(_small_cfg(), runs=2, snaps=4)
+    X, Y, T = train.make_dataset(cfg)
+    blob0 = torch.as_tensor(inputs.gnn_blob(0, 2, s_delta=1e-4), device="cuda")
+    a = train.Trainer(blob0.clone(), 2, shuffle_seed=5)
+    for _ in range(6):
+        a.step(X, Y, T, 1e9, batch=3)
+    b = train.Trainer(blob0.clone(), 2, shuffle_seed=5)
+    for _ in range(3):
+        b.step(X, Y, T, 1e9, batch=3)
+    path = str(tmp_path / "ck.npz")
+    b.save(path)
+    c = train.Trainer(torch.zeros_like(blob0), 2, shuffle_seed=99)
+    c.load(path)
+    for _ in range(3):
+        c.step(X, Y, T, 1e9, batch=3)
+    assert torch.equal(a.blob, c.blob)
+    assert torch.equal(a.m, c.m) and torch.equal(a.v, c.v)
+
+
+def test_trained_collision_beats_bgk_on_held_out_flows():
+    tr, rep = train.train(_small_cfg(), steps=300, batch=16, held_out_runs=4, log_every=50)
+    print({k: v for k, v in rep.items() if k != "history"}, rep["history"])
+    assert rep["heldout_rel_loss_before"] > 0.5
+    assert rep["heldout_rel_loss_after"] < 1.0
+    assert rep["train_rel_loss_after"] < 1.0
