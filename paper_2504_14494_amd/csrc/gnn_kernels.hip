@@ -193,12 +193,12 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
     b2[t] = load_bias(bias, F.B2 + t, lane);
   }
   // Normalisation constants of the 8 features this lane feeds (k = 8q + j).
-  float mu[8], sg[8];
+  float mu[8], isg[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     int k = 8 * q + j;
     mu[j] = k < NFEAT ? cst[C_MU + k] : 0.0f;
-    sg[j] = k < NFEAT ? cst[C_SIGMA + k] : 1.0f;
+    isg[j] = k < NFEAT ? 1.0f / cst[C_SIGMA + k] : 0.0f;
   }
   const long long gxn = (nx + 15) / 16;
   const long long ngroups = (long long)batch * ny * gxn;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         float raw = q == 0 ? all[j] : (j < NFEAT - 8 ? all[8 + (j < NFEAT - 8 ? j : 0)] : 0.0f);
-        feat[j] = (q == 0 || j < NFEAT - 8) ? (raw - mu[j]) / sg[j] : 0.0f;
+        feat[j] = (q == 0 || j < NFEAT - 8) ? (raw - mu[j]) * isg[j] : 0.0f;
       }
     }
     u32x4 xb = {pack_bf16(feat[0], feat[1]), pack_bf16(feat[2], feat[3]),
@@ -259,12 +259,12 @@ constexpr int TILE = 16;            // receivers per tile edge
 constexpr int HALO = TILE + 2;      // node states of the tile and its 1-node ring
 constexpr int HNODES = HALO * HALO;
 
-// Node state fragment (k-step s, lane group q) of LDS node ln.  The 8
-// 16-byte chunks of a node are XOR-swizzled with the node index so that
-// 16 lanes reading the same chunk of 16 consecutive nodes spread over banks.
-__device__ __forceinline__ u32x4 lds_frag(const uint8_t *hs, int ln, int chunk) {
-  return *(const u32x4 *)(hs + ln * 128 + ((chunk ^ (ln & 7)) << 4));
-}
+// LDS node stride: 128 B of state + 16 B of padding.  16 lanes reading the
+// same 16-byte chunk of 16 consecutive nodes then touch 16 disjoint groups of
+// 4 banks (144 B = 36 banks apart, mod 64), so the reads are conflict-free,
+// and the address of a neighbour's chunk is the lane's own address plus a
+// compile-time offset.
+constexpr int kNodeBytes = 144;
 
 __device__ __forceinline__ int wrapi(int a, int n) {
   a %= n;
@@ -321,12 +321,11 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
     const uint16_t *__restrict__ hin, uint16_t *__restrict__ hout,
     uint16_t *__restrict__ save_agg, int batch, int nx, int ny, int round,
     const uint8_t *__restrict__ pack, FragLayout F, HeadArgs args) {
-  __shared__ __attribute__((aligned(16))) uint8_t hs[HNODES * 128];
+  __shared__ __attribute__((aligned(16))) uint8_t hs[HNODES * kNodeBytes];
   __shared__ u32x4 wa_s[8 * 64];
   __shared__ u32x4 wn_s[16 * 64];
-  __shared__ float zb[HEAD ? kWaves * 64 * NOUT : 1];
-  __shared__ double red_m[kThreads];
-  __shared__ unsigned red_f[kThreads];
+  // head outputs of the wave's 64 nodes; reused for the final reduction
+  __shared__ __attribute__((aligned(16))) float zb[HEAD ? kWaves * 64 * NOUT : 1];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
@@ -376,7 +375,7 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
       int ln = k >> 3, c = k & 7;
       int gx = wrapi(x0 - 1 + ln % HALO, nx), gy = wrapi(y0 - 1 + ln / HALO, ny);
       const u32x4 *srcp = (const u32x4 *)(hin + (lat_nodes + (size_t)gy * nx + gx) * HID);
-      *(u32x4 *)(hs + ln * 128 + ((c ^ (ln & 7)) << 4)) = srcp[c];
+      *(u32x4 *)(hs + ln * kNodeBytes + c * 16) = srcp[c];
     }
     __syncthreads();
 
@@ -390,8 +389,13 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
       const u32x4 *wa = wa_s + wo, *wn = wn_s + wo;
       const int tyl = wave * 4 + r;
       const int x = x0 + n, y = y0 + tyl;
-      const int ln_self = (tyl + 1) * HALO + n + 1;
-      u32x4 hn[2] = {lds_frag(hs, ln_self, q), lds_frag(hs, ln_self, 4 + q)};
+      // chunk q of the lower-left neighbour (dx = dy = -1) of this receiver;
+      // every neighbour's chunk is at a constant offset from it
+      const uint8_t *nb = hs + (tyl * HALO + n) * kNodeBytes + q * 16;
+      auto frag_at = [&](int dx, int dy, int s) {
+        return *(const u32x4 *)(nb + ((dy + 1) * HALO + dx + 1) * kNodeBytes + s * 64);
+      };
+      u32x4 hn[2] = {frag_at(0, 0, 0), frag_at(0, 0, 1)};
       f32x4 an[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -399,12 +403,11 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
         an[t] = mfma(wa[(2 * t + 1) * 64], hn[1], an[t]);
       }
       f32x4 agg[4] = {};
-#pragma unroll 2
+      const uint32_t q0 = q == 0 ? 0xffffffffu : 0u;
+#pragma unroll
       for (int d = 1; d < 9; ++d) {
-        const int ln = ln_self + cy(d) * HALO + cx(d);
-        u32x4 hj[2] = {lds_frag(hs, ln, q), lds_frag(hs, ln, 4 + q)};
-        const u32x4 ed = {q == 0 ? (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)) : 0u, 0u, 0u,
-                          0u};
+        u32x4 hj[2] = {frag_at(cx(d), cy(d), 0), frag_at(cx(d), cy(d), 1)};
+        const u32x4 ed = {q0 & (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)), 0u, 0u, 0u};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           f32x4 acc = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
@@ -484,6 +487,9 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
   }
 
   if constexpr (HEAD) {
+    __syncthreads();  // last tile's head outputs consumed
+    double *red_m = (double *)zb;
+    unsigned *red_f = (unsigned *)(zb + 2 * kThreads);
     red_m[threadIdx.x] = mass_acc;
     red_f[threadIdx.x] = flag_acc;
     __syncthreads();

@@ -1,0 +1,172 @@
+"""Accuracy experiments on the GPU: plain BGK against the GNN-corrected
+collision at equal Taylor-Green velocity error (paper: "Taylor-Green Vortex
+Validation" and "Resolution Study"; velocity L2 error as read in R5 of the
+design notes).
+
+The reference is an FP64 BGK run on a fine lattice (n_fine), restricted to
+each coarse lattice at equal physical time (acoustic scaling: one coarse
+step on a lattice n_fine/c spans c fine steps).  Comparing with this
+reference rather than the analytic decay removes the acoustic transient of
+the uniform-density start, which every run shares.  All stepping, moments
+and restriction run in liblbmgnn.so.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import gnn, inputs, lbm
+
+
+def _tau(u0, re, n):
+    return 3.0 * u0 * n / re + 0.5
+
+
+def _velocity(g32: torch.Tensor):
+    _, ux, uy, _ = lbm.lbm_moments(g32, fields=True, sums=False)
+    return ux, uy
+
+
+def _rel_err(ux, uy, rx, ry):
+    num = ((ux.double() - rx) ** 2 + (uy.double() - ry) ** 2).sum()
+    den = (rx ** 2 + ry ** 2).sum()
+    return math.sqrt((num / den).item())
+
+
+def fine_reference(u0, re, phase, n_fine, coarse_sizes, times_fine):
+    """Velocity fields of an FP64 run restricted onto each coarse lattice:
+    {n: {t_fine: (ux, uy) float64}}."""
+    rho, ux, uy = inputs.tgv_velocity(n_fine, n_fine, u0, x0=phase[0] * n_fine,
+                                      y0=phase[1] * n_fine)
+    tau_f = _tau(u0, re, n_fine)
+    lat = lbm.Lattice(n_fine, n_fine, dtype=torch.float64).init(rho, ux, uy)
+    out = {n: {} for n in coarse_sizes}
+    done = 0
+    for t in sorted(times_fine):
+        lat.step_bgk(tau_f, t - done)
+        done = t
+        for n in coarse_sizes:
+            c = n_fine // n
+            gc = lbm.lbm_restrict(lat.a, c, tau_f, _tau(u0, re, n), pull=False, unstream=False)
+            vx, vy = _velocity(gc)
+            out[n][t] = (vx.double(), vy.double())
+    return out
+
+
+def coarse_run(n, u0, re, phase, steps_list, blob=None, rounds=2):
+    """Velocity of a coarse run at the given step counts; BGK when blob is
+    None.  Returns ({steps: (ux, uy)}, fallback count, seconds)."""
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0, x0=phase[0] * n, y0=phase[1] * n,
+                                      dtype=np.float32)
+    tau = float(np.float32(_tau(u0, re, n)))
+    if blob is None:
+        lat = lbm.Lattice(n, n).init(rho, ux, uy)
+    else:
+        lat = gnn.GnnLattice(n, n, blob, rounds).init(rho, ux, uy)
+    res, done = {}, 0
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    ms = 0.0
+    for s in sorted(steps_list):
+        t0.record()
+        if blob is None:
+            lat.step_bgk(tau, s - done)
+        else:
+            lat.step_gnn(tau, s - done)
+        t1.record()
+        torch.cuda.synchronize()
+        ms += t0.elapsed_time(t1)
+        done = s
+        res[s] = _velocity(lat.a)
+    fb = int(lat.n_fallback.item()) if blob is not None else 0
+    return res, fb, ms * 1e-3
+
+
+def fixed_error_report(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_fine=512,
+                       n_gnn=128, bgk_sizes=(128, 256), coarse_steps=(250, 500, 1000),
+                       mlups_bgk=None, mlups_gnn=None):
+    """Velocity errors of the trained GNN at n_gnn and of BGK on bgk_sizes
+    against the restricted FP64 reference, and the time each needs to reach
+    the last time, projected from the large-lattice MLUPS when given."""
+    sizes = sorted(set(bgk_sizes) | {n_gnn})
+    times = sorted({m * (n_fine // n_gnn) for m in coarse_steps})
+    ref = fine_reference(u0, re, phase, n_fine, sizes, times)
+    rep = {"u0": u0, "re": re, "n_fine": n_fine, "coarse_steps_at_n_gnn": list(coarse_steps),
+           "errors": {}, "fallback_steps": 0}
+    gsteps = list(coarse_steps)
+    gres, fb, gsec = coarse_run(n_gnn, u0, re, phase, gsteps, blob, rounds)
+    rep["fallback_steps"] = fb
+    rep["errors"][f"gnn_{n_gnn}"] = [
+        _rel_err(*gres[m], *ref[n_gnn][m * (n_fine // n_gnn)]) for m in gsteps]
+    secs = {f"gnn_{n_gnn}": gsec}
+    for n in bgk_sizes:
+        steps = [m * n // n_gnn for m in coarse_steps]
+        bres, _, bsec = coarse_run(n, u0, re, phase, steps)
+        rep["errors"][f"bgk_{n}"] = [
+            _rel_err(*bres[s], *ref[n][s * (n_fine // n)]) for s in steps]
+        secs[f"bgk_{n}"] = bsec
+    rep["measured_seconds"] = secs
+    # smallest BGK lattice at least as accurate as the GNN at the last time
+    e_g = rep["errors"][f"gnn_{n_gnn}"][-1]
+    match = [n for n in bgk_sizes if rep["errors"][f"bgk_{n}"][-1] <= e_g]
+    rep["bgk_lattice_at_gnn_error"] = min(match) if match else None
+    if mlups_bgk and mlups_gnn:
+        last = coarse_steps[-1]
+        proj = {f"gnn_{n_gnn}": n_gnn * n_gnn * last / (mlups_gnn * 1e6)}
+        for n in bgk_sizes:
+            proj[f"bgk_{n}"] = n * n * (last * n // n_gnn) / (mlups_bgk * 1e6)
+        rep["projected_seconds_at_large_lattice_mlups"] = proj
+    return rep
+
+
+def _energy(ux, uy):
+    return 0.5 * float(((ux.double() ** 2) + (uy.double() ** 2)).sum().item())
+
+
+def long_rollout(blob, rounds=2, n=2048, u0=0.05, re=1e4, steps=20000, sample_every=2000,
+                 n_sample=256, threshold=1e-6):
+    """Long corrected rollout with the per-step fallback gate, beside an FP64
+    BGK run of the same flow.  Every `sample_every` steps both are sampled on
+    every (n/n_sample)-th node (injection) and the kinetic energies are
+    compared; mass and momentum are summed in FP64 on the GPU."""
+    tau = _tau(u0, re, n)
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
+    lat = gnn.GnnLattice(n, n, blob, rounds, threshold).init(rho, ux, uy)
+    ref = lbm.Lattice(n, n, dtype=torch.float64).init(*inputs.tgv_velocity(n, n, u0))
+    c = n // n_sample
+    _, _, _, s0 = lat.moments()
+    s0 = s0.cpu().numpy()
+    nu = (float(np.float32(tau)) - 0.5) / 3.0
+    k2 = 2.0 * (2.0 * math.pi / n) ** 2
+    rows, done, ms = [], 0, 0.0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t32 = float(np.float32(tau))
+    while done < steps:
+        k = min(sample_every, steps - done)
+        e0.record()
+        lat.step_gnn(t32, k)
+        e1.record()
+        ref.step_bgk(tau, k)
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done += k
+        _, gx, gy, sums = lat.moments(fields=True)
+        gref = lbm.lbm_restrict(ref.a, 1, tau, tau, pull=False, unstream=False)
+        rx, ry = _velocity(gref)
+        e_gnn = _energy(gx[::c, ::c], gy[::c, ::c])
+        e_ref = _energy(rx[::c, ::c], ry[::c, ::c])
+        e_an = _energy(*[torch.as_tensor(a[::c, ::c]) for a in inputs.tgv_velocity(n, n, u0)[1:]]) \
+            * math.exp(-2.0 * nu * k2 * done)
+        s = sums.cpu().numpy()
+        rows.append({"step": done, "energy_err_vs_fp64": abs(e_gnn - e_ref) / e_ref,
+                     "energy_err_fp64_vs_analytic": abs(e_ref - e_an) / e_an,
+                     "mass_drift": abs(s[0] - s0[0]) / s0[0],
+                     "momentum": [float(s[1]), float(s[2])],
+                     "fallback_steps": int(lat.n_fallback.item()),
+                     "min_f": float(s[6])})
+    return {"n": n, "u0": u0, "re": re, "tau": tau, "steps": steps,
+            "mlups": n * n * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
+            "samples": rows}
