@@ -1,10 +1,17 @@
 """Throughput benchmark of the LBM-GNN hot path on one MI355X.
 
 Headline: MLUPS of the fused D2Q9 BGK pull step on the 8192x8192 Taylor-Green
-workload (FP32 SoA, Re = 1000, u0 = 0.04), with the populations resident in
-HBM.  Beside it: the GNN-corrected step on 2048x2048, the roofline of the BGK
-kernel (algorithmic 72 B per lattice update against 8 TB/s), and the FP64 CPU
-oracle timed on the host on a bounded sample.
+workload (FP32, row-interleaved SoA, Re = 1000, u0 = 0.04), with the
+populations resident in HBM, and the roofline of that kernel (algorithmic
+72 B per lattice update against 8 TB/s, HBM traffic from the committed
+rocprofv3 counters).  Beside it:
+  gnn          the GNN-corrected step on 2048x2048 (MLUPS, MFMA and GELU/VALU
+               rooflines, committed counter utilisation);
+  fixed_error  the network trained on self-generated data (about 10 s), then
+               its 128^2 rollout against plain BGK at 128^2 and 256^2, all
+               measured against a restricted FP64 512^2 run, with the time each
+               needs (measured and projected from the large-lattice MLUPS);
+  cpu_baseline the FP64 CPU oracle timed on the host on a bounded sample.
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -25,9 +32,28 @@ BGK_BYTES_PER_LU = 72           # 9 FP32 loads + 9 FP32 stores per node
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bgk_pull_8192_traffic.json")
 
 
-def _src_hash(path):
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+CSRC = os.path.join(ROOT, "paper_2504_14494_amd", "csrc")
+GNN_PMC_FILE = os.path.join(ROOT, "profiles", "gnn_step_2048_counters.json")
+
+
+def _read(name):
+    with open(os.path.join(CSRC, name), "rb") as fh:
+        return fh.read()
+
+
+def bgk_src_hash():
+    """Hash of the source the BGK step is compiled from: the shared device
+    header and the kernel with its launcher."""
+    body = _read("lbm_kernels.hip")
+    a = body.index(b"constexpr int kBgkThreads")
+    b = body.index(b"// ------", a)
+    return hashlib.sha256(_read("lbm_common.hpp") + body[a:b]).hexdigest()[:16]
+
+
+def gnn_src_hash():
+    """Hash of the sources of the corrected step's kernels."""
+    return hashlib.sha256(_read("gnn_common.hpp") + _read("gnn_layout.hpp") +
+                          _read("gnn_kernels.hip") + _read("lbm_common.hpp")).hexdigest()[:16]
 
 
 def bgk_leg(n, re, u0, steps, warmup):
@@ -105,6 +131,47 @@ def gnn_leg(n, steps, warmup):
             "steps": steps, "fallback_steps": fallbacks}
 
 
+# Corrected step, 2048^2, per node: minimum MFMA work of the network
+# (12->64->64 encoder, two rounds of the exactly split edge layer and node
+# update, 64->10 head) and GELU evaluations.
+GNN_MAC_PER_NODE = 12 * 64 + 64 * 64 + 2 * (64 * 64 + 64 * 64 + 64 * 128) + 64 * 10
+GNN_GELU_PER_NODE = 128 + 2 * (8 * 64 + 64)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# FP32 VALU without packed math: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
+# A GELU costs 5 full-rate ops and 2 quarter-rate transcendentals = 13 slots.
+GELU_PEAK_PER_S = 256 * 64 * 2.4e9 / 13
+
+
+def gnn_roofline(ms_per_step, nodes):
+    """MFMA and VALU (GELU) rooflines of the corrected step; counters of the
+    committed rocprofv3 summary when it matches the kernel source."""
+    sec = ms_per_step * 1e-3
+    mfma_tf = 2.0 * GNN_MAC_PER_NODE * nodes / sec / 1e12
+    gelu_rate = GNN_GELU_PER_NODE * nodes / sec
+    r = {"roofline_mfma": {"bound": "mfma", "achieved": round(mfma_tf, 1),
+                           "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(mfma_tf / MFMA_BF16_PEAK_TFLOPS, 4)},
+         "roofline_alu": {"bound": "alu", "achieved": round(gelu_rate / 1e12, 3),
+                          "peak": round(GELU_PEAK_PER_S / 1e12, 3), "unit": "T GELU/s",
+                          "frac": round(gelu_rate / GELU_PEAK_PER_S, 4)}}
+    t = _committed(GNN_PMC_FILE, gnn_src_hash())
+    r["counters"] = None if t is None else t.get("utilisation")
+    return r
+
+
+def fixed_error_leg(mlups_bgk, mlups_gnn):
+    """Train on self-generated data, then trained GNN at 128^2 against plain
+    BGK at 128^2 and 256^2, all against a restricted FP64 512^2 run."""
+    from paper_2504_14494_amd import experiments, train
+    t0 = time.perf_counter()
+    tr, rep = train.train(train.DataConfig(), steps=2000, batch=32)
+    out = {"train_seconds": round(time.perf_counter() - t0, 1),
+           "heldout_loss_over_bgk": rep["heldout_rel_loss_after"]}
+    out.update(experiments.fixed_error_report(tr.blob, mlups_bgk=mlups_bgk,
+                                              mlups_gnn=mlups_gnn))
+    return out
+
+
 def cpu_leg():
     import numpy as np
     import oracle
@@ -122,17 +189,21 @@ def cpu_leg():
                       f"{steps} steps, single thread ({dt:.1f} s)"}
 
 
-def traffic_entry(src_path):
-    """Per-launch HBM bytes from the committed rocprofv3 PMC summary, or None
-    if it is missing or was taken on a different kernel source."""
+def _committed(path, src_hash):
+    """A committed rocprofv3 counter summary, or None if it is missing or was
+    taken on a different kernel source."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256_16") != _src_hash(src_path):
-        return None
-    return t.get("bytes_per_launch")
+    return t if t.get("source_sha256_16") == src_hash else None
+
+
+def traffic_entry():
+    """Per-launch HBM bytes of the BGK step from the committed PMC summary."""
+    t = _committed(TRAFFIC_FILE, bgk_src_hash())
+    return None if t is None else t.get("bytes_per_launch")
 
 
 def main():
@@ -145,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gnn", action="store_true")
     ap.add_argument("--gnn-steps", type=int, default=20)
+    ap.add_argument("--no-fixed-error", action="store_true",
+                    help="skip training the network (about 10 s) and the rollout comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -159,11 +232,10 @@ def main():
 
     bgk = bgk_leg(args.n, args.re, 0.04, args.steps, args.warmup)
     cp = copy_leg(args.n)
-    src = os.path.join(ROOT, "paper_2504_14494_amd", "csrc", "lbm_kernels.hip")
     achieved = BGK_BYTES_PER_LU * args.n * args.n / (bgk["ms_per_step"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_entry(src),
+            "traffic": traffic_entry(),
             "kernel": "bgk_pull_kernel<float>",
             "copy_ceiling_gbs": round(cp["gbs"], 1),
             "frac_of_copy": round(achieved / cp["gbs"], 4)}
@@ -189,10 +261,18 @@ def main():
     }
     if not args.no_gnn:
         try:
-            out["gnn"] = gnn_leg(2048, args.gnn_steps, 3)
-            out["gnn"]["bgk_mlups_same_gpu"] = out["value"]
+            g = gnn_leg(2048, args.gnn_steps, 3)
+            g["bgk_mlups_same_gpu"] = out["value"]
+            g["step_over_bgk_step"] = round(out["value"] / g["mlups"], 1)
+            g.update(gnn_roofline(g["ms_per_step"], 2048 * 2048))
+            out["gnn"] = g
         except Exception as e:  # reported, never hidden
             out["gnn"] = {"error": repr(e)}
+    if not args.no_fixed_error and "error" not in out.get("gnn", {"error": 1}):
+        try:
+            out["fixed_error"] = fixed_error_leg(out["value"], out["gnn"]["mlups"])
+        except Exception as e:
+            out["fixed_error"] = {"error": repr(e)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_leg()
     print(json.dumps(out), flush=True)

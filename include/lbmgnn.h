@@ -63,6 +63,20 @@ int lbm_init(float *g, int nx, int ny, const float *rho, const float *ux,
 int lbm_init_f64(double *g, int nx, int ny, const double *rho,
                  const double *ux, const double *uy, void *stream);
 
+/* Initial state on the slow manifold.  The pre-collision state is f^eq(rho, u)
+ * plus the first-order Chapman-Enskog non-equilibrium
+ * -(tau w_i rho / c_s^2) Q_i : S, with Q_i = e_i e_i - c_s^2 I and S the
+ * symmetric velocity gradient taken by second-order central differences on
+ * the periodic lattice (a textbook construction, not part of the paper's
+ * method).  Like every state the steps consume, g holds its post-collision
+ * image, f^eq - ((tau - 1) w_i rho / c_s^2) Q_i : S.  Unlike lbm_init it does
+ * not excite the period-2 non-hydrodynamic mode, which at tau near 1/2 decays
+ * only by |1 - 1/tau| per step.  Requires tau > 0. */
+int lbm_init_ce(float *g, int nx, int ny, const float *rho, const float *ux, const float *uy,
+                float tau, void *stream);
+int lbm_init_ce_f64(double *g, int nx, int ny, const double *rho, const double *ux,
+                    const double *uy, double tau, void *stream);
+
 /* One time step of Eq. 1 in fused pull form.  g_src holds the post-collision
  * state of step t-1; the kernel gathers g_i(x) = g_src_i(x - e_i)
  * (streaming), forms rho and u, relaxes toward f^eq with omega = 1/tau and
@@ -73,6 +87,13 @@ int lbm_step_bgk(const float *g_src, float *g_dst, int nx, int ny, float tau,
 /* Same in FP64. */
 int lbm_step_bgk_f64(const double *g_src, double *g_dst, int nx, int ny,
                      double tau, void *stream);
+
+/* Streaming alone, the left-hand side of Eq. 1 without the collision:
+ * g_dst_i(x) = g_src_i(x - e_i), periodic, on `batch` lattices stored one
+ * after another ([batch][ny][9][nx]).  Turns a post-collision state into the
+ * next pre-collision state (e.g. to feed gnn_forward).  The buffers must not
+ * overlap. */
+int lbm_stream(const float *g_src, float *g_dst, int nx, int ny, int batch, void *stream);
 
 /* Analytic decaying Taylor-Green field used for the error sums:
  * u_x = -u0 cos(kx X) sin(ky Y) D, u_y = u0 (kx/ky) sin(kx X) cos(ky Y) D,

@@ -52,6 +52,7 @@ def lib():
         L.orc_equilibrium.argtypes = [d, d, d, pd]
         L.orc_moments.argtypes = [pd, i, i, pd, pd, pd]
         L.orc_init_equilibrium.argtypes = [pd, i, i, pd, pd, pd]
+        L.orc_init_ce.argtypes = [pd, i, i, pd, pd, pd, d]
         L.orc_collide_bgk.argtypes = [pd, pd, i, i, d]
         L.orc_stream.argtypes = [pd, pd, i, i]
         L.orc_unstream.argtypes = [pd, pd, i, i]
@@ -117,6 +118,15 @@ def init_equilibrium(rho, ux, uy) -> np.ndarray:
     ny, nx = rho.shape
     f = np.zeros((9, ny, nx))
     lib().orc_init_equilibrium(_p(f), nx, ny, _p(rho), _p(ux), _p(uy))
+    return f
+
+
+def init_ce(rho, ux, uy, tau: float) -> np.ndarray:
+    """Equilibrium plus first-order Chapman-Enskog non-equilibrium."""
+    rho, ux, uy = _f64(rho), _f64(ux), _f64(uy)
+    ny, nx = rho.shape
+    f = np.zeros((9, ny, nx))
+    lib().orc_init_ce(_p(f), nx, ny, _p(rho), _p(ux), _p(uy), float(tau))
     return f
 
 

@@ -49,6 +49,34 @@ void orc_equilibrium(double rho, double ux, double uy, double *feq) {
   }
 }
 
+/* Initial state on the slow manifold (textbook Chapman-Enskog expansion,
+ * Krueger et al., which the paper cites; not part of the paper's method):
+ * f_i = f_i^eq(rho, u) - (tau w_i rho / c_s^2) Q_i : S with
+ * Q_i = e_i e_i - c_s^2 I and S the symmetric velocity gradient, taken by
+ * second-order central differences on the periodic lattice.  Starting from
+ * f^eq alone instead excites the non-hydrodynamic period-2 mode, which is
+ * damped only by |1 - 1/tau| per step. */
+void orc_init_ce(double *f, int nx, int ny, const double *rho, const double *ux,
+                 const double *uy, double tau) {
+  size_t plane = (size_t)nx * ny;
+  double feq[9];
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t n = (size_t)y * nx + x;
+      size_t xp = (size_t)y * nx + (x + 1) % nx, xm = (size_t)y * nx + (x + nx - 1) % nx;
+      size_t yp = (size_t)((y + 1) % ny) * nx + x, ym = (size_t)((y + ny - 1) % ny) * nx + x;
+      double dux_dx = 0.5 * (ux[xp] - ux[xm]), dux_dy = 0.5 * (ux[yp] - ux[ym]);
+      double duy_dx = 0.5 * (uy[xp] - uy[xm]), duy_dy = 0.5 * (uy[yp] - uy[ym]);
+      double sxx = dux_dx, syy = duy_dy, sxy = 0.5 * (dux_dy + duy_dx);
+      orc_equilibrium(rho[n], ux[n], uy[n], feq);
+      for (int i = 0; i < 9; ++i) {
+        double qs = (EX[i] * EX[i] - CS2) * sxx + 2.0 * EX[i] * EY[i] * sxy +
+                    (EY[i] * EY[i] - CS2) * syy;
+        f[i * plane + n] = feq[i] - tau * W[i] * rho[n] / CS2 * qs;
+      }
+    }
+}
+
 /* Macroscopic moments: rho = sum_i f_i, rho u = sum_i e_i f_i. */
 static void node_moments(const double *f, size_t plane, size_t n, double *rho,
                          double *ux, double *uy) {

@@ -21,6 +21,7 @@ LBM_WS_MSE = 5
 
 EXPORTS = [
     "lbm_last_error", "lbm_init", "lbm_init_f64", "lbm_step_bgk", "lbm_step_bgk_f64",
+    "lbm_stream", "lbm_init_ce", "lbm_init_ce_f64",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
     "lbm_step_gnn", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
     "lbm_workspace_bytes",
@@ -62,6 +63,9 @@ def load(path: str = LIB_PATH):
         "lbm_init_f64": ([vp, i, i, vp, vp, vp, vp], i),
         "lbm_step_bgk": ([vp, vp, i, i, f, vp], i),
         "lbm_step_bgk_f64": ([vp, vp, i, i, d, vp], i),
+        "lbm_stream": ([vp, vp, i, i, i, vp], i),
+        "lbm_init_ce": ([vp, i, i, vp, vp, vp, f, vp], i),
+        "lbm_init_ce_f64": ([vp, i, i, vp, vp, vp, d, vp], i),
         "lbm_moments": ([vp, i, i, vp, vp, vp, ctypes.POINTER(LbmTgv), vp, vp, sz, vp], i),
         "lbm_restrict": ([vp, i, i, i, d, d, i, i, vp, vp], i),
         "lbm_copy": ([vp, vp, sz, vp], i),

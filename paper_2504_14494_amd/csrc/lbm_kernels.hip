@@ -31,6 +31,38 @@ __global__ void init_kernel(T *__restrict__ g, int nx, int ny, const T *__restri
   for (int i = 0; i < 9; ++i) g[pidx(nx, y, i, x)] = geq_shifted<T>(i, r - T(1), r, u, v, uu);
 }
 
+// Post-collision image of the first-order Chapman-Enskog state: the
+// pre-collision state f^eq - (tau w_i rho / c_s^2) Q_i : S (Q_i = e_i e_i -
+// c_s^2 I, S the symmetric velocity gradient by second-order central
+// differences, periodic) after one BGK collision, which scales its
+// non-equilibrium part by 1 - 1/tau: f^eq - ((tau - 1) w_i rho / c_s^2) Q_i : S.
+// A state on the slow manifold: it does not excite the period-2 mode that a
+// pure equilibrium start launches.
+template <typename T>
+__global__ void init_ce_kernel(T *__restrict__ g, int nx, int ny, const T *__restrict__ rho,
+                               const T *__restrict__ ux, const T *__restrict__ uy, T tau) {
+  size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (size_t)nx * ny) return;
+  int x = (int)(n % nx), y = (int)(n / nx);
+  size_t row = (size_t)y * nx;
+  size_t xp = row + (x + 1 == nx ? 0 : x + 1), xm = row + (x == 0 ? nx - 1 : x - 1);
+  size_t yp = (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x;
+  size_t ym = (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
+  T sxx = T(0.5) * (ux[xp] - ux[xm]);
+  T syy = T(0.5) * (uy[yp] - uy[ym]);
+  T sxy = T(0.25) * ((ux[yp] - ux[ym]) + (uy[xp] - uy[xm]));
+  T r = rho[n], u = ux[n], v = uy[n];
+  T uu = u * u + v * v;
+  const T cs2 = T(1) / T(3);
+  T pre = (tau - T(1)) * r / cs2;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    T qs = (T(cx(i) * cx(i)) - cs2) * sxx + T(2 * cx(i) * cy(i)) * sxy +
+           (T(cy(i) * cy(i)) - cs2) * syy;
+    g[pidx(nx, y, i, x)] = geq_shifted<T>(i, r - T(1), r, u, v, uu) - pre * wgt<T>(i) * qs;
+  }
+}
+
 // ------------------------------------------------------------ BGK, fused ---
 
 constexpr int kBgkThreads = 256;
@@ -63,6 +95,21 @@ int launch_bgk(const T *src, T *dst, int nx, int ny, T tau, hipStream_t s) {
   hipLaunchKernelGGL(bgk_pull_kernel<T>, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s, src,
                      dst, nx, ny, bx, T(1) / tau);
   return launch_check("bgk_pull_kernel");
+}
+
+// Streaming alone (the left-hand side of Eq. 1): dst_i(x) = src_i(x - e_i).
+template <typename T>
+__global__ __launch_bounds__(kBgkThreads) void stream_kernel(const T *__restrict__ src,
+                                                             T *__restrict__ dst, int nx, int ny,
+                                                             int bx) {
+  int y = blockIdx.x / bx;
+  int x = (blockIdx.x - y * bx) * kBgkThreads + threadIdx.x;
+  if (x >= nx) return;
+  T g[9];
+  pull9(src, nx, ny, x, y, g);
+  T *d = dst + (size_t)y * 9 * nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[(size_t)i * nx] = g[i];
 }
 
 // ----------------------------------------------------- moments + sums ---
@@ -241,6 +288,29 @@ static int init_impl(T *g, int nx, int ny, const T *rho, const T *ux, const T *u
   return launch_check("init_kernel");
 }
 
+template <typename T>
+static int init_ce_impl(T *g, int nx, int ny, const T *rho, const T *ux, const T *uy, T tau,
+                        void *stream) {
+  if (!g || !rho || !ux || !uy) return fail(LBM_EINVAL, "lbm_init_ce: null pointer");
+  if (!lattice_ok(nx, ny)) return fail(LBM_EINVAL, "lbm_init_ce: bad lattice %d x %d", nx, ny);
+  if (!(tau > T(0))) return fail(LBM_EINVAL, "lbm_init_ce: tau must be positive");
+  if (int rc = check_device()) return rc;
+  size_t nodes = (size_t)nx * ny;
+  hipLaunchKernelGGL(init_ce_kernel<T>, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0,
+                     as_stream(stream), g, nx, ny, rho, ux, uy, tau);
+  return launch_check("init_ce_kernel");
+}
+
+extern "C" int lbm_init_ce(float *g, int nx, int ny, const float *rho, const float *ux,
+                           const float *uy, float tau, void *stream) {
+  return init_ce_impl(g, nx, ny, rho, ux, uy, tau, stream);
+}
+
+extern "C" int lbm_init_ce_f64(double *g, int nx, int ny, const double *rho, const double *ux,
+                               const double *uy, double tau, void *stream) {
+  return init_ce_impl(g, nx, ny, rho, ux, uy, tau, stream);
+}
+
 extern "C" int lbm_init(float *g, int nx, int ny, const float *rho, const float *ux,
                         const float *uy, void *stream) {
   return init_impl(g, nx, ny, rho, ux, uy, stream);
@@ -271,6 +341,26 @@ extern "C" int lbm_step_bgk(const float *g_src, float *g_dst, int nx, int ny, fl
 extern "C" int lbm_step_bgk_f64(const double *g_src, double *g_dst, int nx, int ny,
                                 double tau, void *stream) {
   return step_bgk_impl(g_src, g_dst, nx, ny, tau, stream);
+}
+
+extern "C" int lbm_stream(const float *g_src, float *g_dst, int nx, int ny, int batch,
+                          void *stream) {
+  if (!g_src || !g_dst) return fail(LBM_EINVAL, "lbm_stream: null pointer");
+  if (batch < 1 || !lattice_ok(nx, ny) || (long long)batch * nx * ny >= (1LL << 31))
+    return fail(LBM_EINVAL, "lbm_stream: bad sizes");
+  size_t per = (size_t)9 * nx * ny;
+  if (overlap(g_src, g_dst, per * batch * sizeof(float)))
+    return fail(LBM_EINVAL, "lbm_stream: source and destination overlap");
+  if (int rc = check_device()) return rc;
+  int bx = (nx + kBgkThreads - 1) / kBgkThreads;
+  long long blocks = (long long)bx * ny;
+  if (blocks > 0x7fffffffLL) return fail(LBM_EINVAL, "lbm_stream: lattice too large");
+  for (int b = 0; b < batch; ++b) {
+    hipLaunchKernelGGL(stream_kernel<float>, dim3((unsigned)blocks), dim3(kBgkThreads), 0,
+                       as_stream(stream), g_src + b * per, g_dst + b * per, nx, ny, bx);
+    if (int rc = launch_check("stream_kernel")) return rc;
+  }
+  return LBM_OK;
 }
 
 extern "C" int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux, float *uy,

@@ -135,6 +135,11 @@ class GnnLattice(Lattice):
         self.sync_mass()
         return self
 
+    def init_ce(self, rho, ux, uy, tau: float):
+        super().init_ce(rho, ux, uy, tau)
+        self.sync_mass()
+        return self
+
     def load(self, g):
         super().load(g)
         self.sync_mass()

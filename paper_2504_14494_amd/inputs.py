@@ -43,6 +43,19 @@ def tgv_velocity(nx: int, ny: int, u0: float, x0: float = 0.0,
     return rho.astype(dtype), ux.astype(dtype), uy.astype(dtype)
 
 
+def tgv_pressure_density(nx: int, ny: int, u0: float, x0: float = 0.0, y0: float = 0.0,
+                         dtype=np.float64):
+    """Density that carries the Taylor-Green pressure field at t = 0,
+    rho = 1 + p / c_s^2 with p = -(u0^2 / 4)(cos 2kx X + (kx/ky)^2 cos 2ky Y),
+    the closed-form companion of tgv_velocity (uniform density instead
+    launches an acoustic transient)."""
+    kx, ky = 2 * np.pi / nx, 2 * np.pi / ny
+    X = np.arange(nx, dtype=np.float64)[None, :] - x0
+    Y = np.arange(ny, dtype=np.float64)[:, None] - y0
+    rho = 1.0 - 0.75 * u0 * u0 * (np.cos(2 * kx * X) + (kx / ky) ** 2 * np.cos(2 * ky * Y))
+    return rho.astype(dtype)
+
+
 def tgv_spec(nx: int, ny: int, u0: float, nu: float, t: float,
              x0: float = 0.0, y0: float = 0.0):
     """(u0, kx, ky, x0, y0, nu, t) describing the decaying field."""

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import LbmFallback, LbmTgv, check
 
 __all__ = [
-    "lbm_init", "lbm_step_bgk", "lbm_moments", "lbm_restrict", "lbm_copy",
+    "lbm_init", "lbm_init_ce", "lbm_step_bgk", "lbm_stream", "lbm_moments", "lbm_restrict", "lbm_copy",
     "lbm_workspace_bytes", "Workspace", "Lattice",
 ]
 
@@ -77,6 +77,22 @@ def lbm_init(g: torch.Tensor, rho: torch.Tensor, ux: torch.Tensor, uy: torch.Ten
     return g
 
 
+def lbm_init_ce(g: torch.Tensor, rho: torch.Tensor, ux: torch.Tensor, uy: torch.Tensor,
+                tau: float):
+    """Equilibrium plus first-order Chapman-Enskog non-equilibrium."""
+    dt = g.dtype
+    for t, n in ((g, "g"), (rho, "rho"), (ux, "ux"), (uy, "uy")):
+        _need(t, dt, n)
+    nx, ny = _pop_dims(g)
+    for t in (rho, ux, uy):
+        if tuple(t.shape) != (ny, nx):
+            raise ValueError("fields must be [ny, nx]")
+    fn = _lib.load().lbm_init_ce if dt == torch.float32 else _lib.load().lbm_init_ce_f64
+    check(fn(_ptr(g), nx, ny, _ptr(rho), _ptr(ux), _ptr(uy), float(tau), _stream()),
+          "lbm_init_ce")
+    return g
+
+
 def lbm_step_bgk(src: torch.Tensor, dst: torch.Tensor, tau: float):
     _need(src, src.dtype, "src")
     _need(dst, src.dtype, "dst")
@@ -90,6 +106,23 @@ def lbm_step_bgk(src: torch.Tensor, dst: torch.Tensor, tau: float):
     else:
         raise TypeError("populations must be float32 or float64")
     check(rc, "lbm_step_bgk")
+    return dst
+
+
+def lbm_stream(src: torch.Tensor, dst: torch.Tensor = None):
+    """Streaming only: dst_i(x) = src_i(x - e_i) for [ny, 9, nx] or
+    [batch, ny, 9, nx] FP32 populations."""
+    _need(src, torch.float32, "src")
+    if dst is None:
+        dst = torch.empty_like(src)
+    _need(dst, torch.float32, "dst")
+    if src.shape != dst.shape:
+        raise ValueError("src and dst shapes differ")
+    if src.dim() == 4:
+        batch, (nx, ny) = int(src.shape[0]), _pop_dims(src[0])
+    else:
+        batch, (nx, ny) = 1, _pop_dims(src)
+    check(_lib.load().lbm_stream(_ptr(src), _ptr(dst), nx, ny, batch, _stream()), "lbm_stream")
     return dst
 
 
@@ -153,6 +186,14 @@ class Lattice:
         dt, dev = self.a.dtype, self.a.device
         lbm_init(self.a, *(torch.as_tensor(t, dtype=dt, device=dev).contiguous()
                            for t in (rho, ux, uy)))
+        self.steps = 0
+        return self
+
+    def init_ce(self, rho, ux, uy, tau: float):
+        """Start on the slow manifold (equilibrium + Chapman-Enskog term)."""
+        dt, dev = self.a.dtype, self.a.device
+        lbm_init_ce(self.a, *(torch.as_tensor(t, dtype=dt, device=dev).contiguous()
+                              for t in (rho, ux, uy)), tau)
         self.steps = 0
         return self
 

@@ -46,13 +46,17 @@ class DataConfig:
     u0_range: tuple = (0.02, 0.06)
     re_range: tuple = (1000.0, 5000.0)
     seed: int = 1234
+    # also pair states of a coarse plain-BGK run of the same flow with the
+    # restricted fine targets (the coarse lattice regressed toward the fine run)
+    coarse_pairs: bool = True
 
     @property
     def n_coarse(self):
         return self.n_fine // self.factor
 
     def snapshot_steps(self):
-        """Coarse steps m of the snapshots, spread over the first coarse_steps."""
+        """Coarse steps m >= 1 of the snapshots, spread over the first
+        coarse_steps."""
         stride = max(1, self.coarse_steps // self.snaps)
         return [1 + k * stride for k in range(self.snaps)]
 
@@ -63,21 +67,55 @@ def taus(u0: float, re: float, nf: int, factor: int):
     return 3.0 * nu_f + 0.5, 3.0 * nu_c + 0.5
 
 
+def tgv_fields(n: int, u0: float, phase, dtype=np.float64):
+    """Taylor-Green density (with its pressure field) and velocity on an n^2
+    lattice with the given phase (fractions of the period)."""
+    x0, y0 = phase[0] * n, phase[1] * n
+    _, ux, uy = inputs.tgv_velocity(n, n, u0, x0=x0, y0=y0, dtype=dtype)
+    rho = inputs.tgv_pressure_density(n, n, u0, x0=x0, y0=y0, dtype=dtype)
+    return rho, ux, uy
+
+
 def run_pairs(u0: float, re: float, phase, cfg: DataConfig, device="cuda"):
-    """Training pairs of one fine run: (inputs [S, nc, 9, nc], targets, tau_c)."""
+    """Training pairs of one fine run: (inputs [S, nc, 9, nc], targets, tau_c).
+
+    Both lattices start on the slow manifold (Chapman-Enskog state with the
+    Taylor-Green pressure).  After k steps the buffers hold the
+    post-collision state P_k, and streaming it gives the pre-collision state
+    f_{k+1} at time k + 1; coarse step m spans fine steps 4m..4m+4.  For every
+    snapshot m >= 1:
+        input  = R(f_fine(4m))                 restricted fine pre-collision state
+        target = S_c^-1 R(f_fine(4m + 4))      post-collision state streaming into it
+    and, when cfg.coarse_pairs is set, also input = f_coarse(m) of a coarse
+    plain-BGK run of the same flow with the same target.  The coarse states
+    carry the coarse lattice's own non-hydrodynamic content, which a corrected
+    coarse run meets and restricted fine states never show."""
     nf, fac = cfg.n_fine, cfg.factor
+    nc = nf // fac
     tau_f, tau_c = taus(u0, re, nf, fac)
-    rho, ux, uy = inputs.tgv_velocity(nf, nf, u0, x0=phase[0] * nf, y0=phase[1] * nf)
-    lat = lbm.Lattice(nf, nf, dtype=torch.float64, device=device).init(rho, ux, uy)
-    ins, outs = [], []
-    done = 0
+    lat = lbm.Lattice(nf, nf, dtype=torch.float64, device=device).init_ce(
+        *tgv_fields(nf, u0, phase), tau_f)
+    clat = None
+    tc32 = float(np.float32(tau_c))
+    if cfg.coarse_pairs:
+        clat = lbm.Lattice(nc, nc, device=device).init_ce(
+            *tgv_fields(nc, u0, phase, np.float32), tc32)
+    ins, outs, cins = [], [], []
+    done = cdone = 0
     for m in cfg.snapshot_steps():
-        lat.step_bgk(tau_f, fac * m - done)
-        done = fac * m
+        lat.step_bgk(tau_f, fac * m - 1 - done)             # P_f(4m - 1)
+        done = fac * m - 1
         ins.append(lbm.lbm_restrict(lat.a, fac, tau_f, tau_c, pull=True, unstream=False))
-        lat.step_bgk(tau_f, fac)
+        if clat is not None:
+            clat.step_bgk(tc32, m - 1 - cdone)              # P_c(m - 1)
+            cdone = m - 1
+            cins.append(lbm.lbm_stream(clat.a))
+        lat.step_bgk(tau_f, fac)                            # P_f(4m + 3)
         done += fac
         outs.append(lbm.lbm_restrict(lat.a, fac, tau_f, tau_c, pull=True, unstream=True))
+    if clat is not None:
+        ins += cins
+        outs += outs
     return torch.stack(ins), torch.stack(outs), tau_c
 
 

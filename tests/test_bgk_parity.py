@@ -171,3 +171,29 @@ def test_full_size_8192_sampled_rows(orc):
         errs[y] = (float(e.max()), np.unravel_index(int(e.argmax()), e.shape))
     print("max error per checked row (value, (direction, x)):", errs)
     assert max(v[0] for v in errs.values()) < 1e-7
+
+
+@pytest.mark.parametrize("B,ny,nx", [(1, 5, 7), (3, 16, 33)])
+def test_stream_only_matches_oracle(orc, B, ny, nx):
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=40 + nx)
+    src = _gpu(inputs.planes_to_rows(g))
+    dst = torch.full_like(src, float("nan"))
+    lbm.lbm_stream(src, dst)
+    got = inputs.rows_to_planes(dst.double().cpu().numpy())
+    for b in range(B):
+        assert np.array_equal(got[b], orc.stream(g[b].astype(np.float64)))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-15), (torch.float32, 1e-8)])
+def test_chapman_enskog_start_matches_oracle(orc, dtype, tol):
+    """The library stores the post-collision image of the oracle's
+    pre-collision Chapman-Enskog state."""
+    ny, nx, u0, tau = 12, 20, 0.05, 0.53
+    _, ux, uy = inputs.tgv_velocity(nx, ny, u0, x0=1.5)
+    rho = inputs.tgv_pressure_density(nx, ny, u0, x0=1.5)
+    g = torch.empty((ny, 9, nx), dtype=dtype, device="cuda")
+    lbm.lbm_init_ce(g, _gpu(rho, dtype), _gpu(ux, dtype), _gpu(uy, dtype), tau)
+    r64, ux64, uy64 = (np.asarray(a, dtype=np.float32 if dtype == torch.float32 else np.float64)
+                       for a in (rho, ux, uy))
+    ref = orc.collide_bgk(orc.init_ce(r64, ux64, uy64, tau), tau)
+    assert np.abs(_host_pop(g) + _w(orc) - ref).max() < tol

@@ -16,21 +16,22 @@ pytestmark = pytest.mark.gpu
 
 
 def test_pairs_match_oracle_generated_pairs(orc):
-    cfg = train.DataConfig(n_fine=32, factor=4, runs=1, snaps=2, coarse_steps=6, seed=3)
+    """Pairs from the library's FP64 runs and restriction against pairs built
+    from the oracle's runs: input R(f(4m)), target S_c^-1 R(f(4m + 4)), both
+    lattices started on the slow manifold."""
+    cfg = train.DataConfig(n_fine=32, factor=4, runs=1, snaps=2, coarse_steps=6, seed=3,
+                           coarse_pairs=False)
     u0, re, ph = 0.05, 1500.0, (0.3, 0.7)
     X, Y, tau_c = train.run_pairs(u0, re, ph, cfg)
     tau_f, tc = train.taus(u0, re, 32, 4)
     assert tc == tau_c
-    rho, ux, uy = inputs.tgv_velocity(32, 32, u0, x0=ph[0] * 32, y0=ph[1] * 32)
-    f0 = orc.init_equilibrium(rho, ux, uy)
+    rho, ux, uy = train.tgv_fields(32, u0, ph)
+    f0 = orc.init_ce(rho, ux, uy, tau_f)          # pre-collision state at t = 0
     w = orc.lattice()[2][:, None, None]
     for k, m in enumerate(cfg.snapshot_steps()):
-        # the library streams post-collision states: after 4m of its steps the
-        # next pre-collision state is the oracle's state after 4m + 1 steps
-        f = orc.bgk_run(f0, tau_f, 4 * m + 1)
+        f = orc.bgk_run(f0, tau_f, 4 * m)
         xin = orc.restrict(f, 4, tau_f, tau_c)
-        ftgt = orc.bgk_run(f, tau_f, 4)
-        yt = orc.restrict(ftgt, 4, tau_f, tau_c, unstream_=True)
+        yt = orc.restrict(orc.bgk_run(f, tau_f, 4), 4, tau_f, tau_c, unstream_=True)
         gx = inputs.rows_to_planes(X[k].double().cpu().numpy()) + w
         gy = inputs.rows_to_planes(Y[k].double().cpu().numpy()) + w
         assert np.abs(gx - xin).max() < 1e-7
