@@ -7,6 +7,8 @@ populations resident in HBM, and the roofline of that kernel (algorithmic
 rocprofv3 counters).  Beside it:
   gnn          the GNN-corrected step on 2048x2048 (MLUPS, MFMA and GELU/VALU
                rooflines, committed counter utilisation);
+  gnn_per_node the paper's Fig. 2 per-node network fused into the pull step,
+               on the headline lattice, and its overhead over the BGK step;
   fixed_error  the network trained on self-generated data (about 10 s), then
                its 128^2 rollout against plain BGK at 128^2 and 256^2, all
                measured against a restricted FP64 512^2 run, with the time each
@@ -172,6 +174,34 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     return out
 
 
+def simple_leg(n, steps, warmup, ms_bgk):
+    """The paper's Fig. 2 per-node network fused into the pull step, on the
+    headline lattice, with the fallback gate on; overhead against the plain
+    BGK step measured on the same lattice."""
+    import numpy as np
+    import torch
+    from paper_2504_14494_amd import gnn, inputs
+
+    u0, re = 0.04, 1000.0
+    _, tau = inputs.tgv_params(n, u0, re)
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
+    blob = torch.as_tensor(inputs.gnn_blob(0, 0, s_delta=1e-4, u0=u0), device="cuda")
+    lat = gnn.GnnLattice(n, n, blob, rounds=0).init(rho, ux, uy)
+    tau32 = float(np.float32(tau))
+    lat.step_gnn(tau32, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step_gnn(tau32, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"n": n, "ms_per_step": ms, "mlups": n * n / (ms * 1e-3) / 1e6, "steps": steps,
+            "fallback_steps": int(lat.n_fallback.item()),
+            "overhead_vs_bgk": round(ms / ms_bgk - 1.0, 4),
+            "network": "per-node 12->64->64 ReLU, 64->10 head, no message passing"}
+
+
 def cpu_leg():
     import numpy as np
     import oracle
@@ -268,6 +298,12 @@ def main():
             out["gnn"] = g
         except Exception as e:  # reported, never hidden
             out["gnn"] = {"error": repr(e)}
+    if not args.no_gnn:
+        try:
+            out["gnn_per_node"] = simple_leg(args.n, max(10, args.steps // 10), 5,
+                                             bgk["ms_per_step"])
+        except Exception as e:
+            out["gnn_per_node"] = {"error": repr(e)}
     if not args.no_fixed_error and "error" not in out.get("gnn", {"error": 1}):
         try:
             out["fixed_error"] = fixed_error_leg(out["value"], out["gnn"]["mlups"])

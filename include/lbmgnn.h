@@ -151,7 +151,9 @@ int lbm_copy(const float *src, float *dst, size_t n, void *stream);
  * delta f = s_delta * P z_{1..9}, P the orthogonal projector onto the null
  * space of the mass and momentum moments.  Weights and stored activations
  * are BF16 (round to nearest even) with FP32 accumulation; the head output
- * and the collision are FP32.  1 <= n_rounds <= 4. */
+ * and the collision are FP32.  0 <= n_rounds <= 4 for the layout queries;
+ * the message-passing entry points need n_rounds >= 1 (n_rounds = 0 is the
+ * per-node network of lbm_step_simple). */
 size_t gnn_param_count(int n_rounds);
 size_t gnn_blob_len(int n_rounds);
 
@@ -203,6 +205,23 @@ int gnn_backward(const float *dL_dgpost, const float *g_pre, const void *saved,
                  const float *params, int n_rounds, float *grad,
                  void *workspace, size_t ws_bytes, void *stream);
 
+/* The per-node corrected collision of the paper's Fig. 2 network: the same
+ * features, a 12 -> 64 -> 64 MLP with ReLU and the 64 -> 10 head (tau_adj,
+ * projected delta f, Eq. 3), with no message passing, fused into the pull
+ * step (one read and one write of the nine populations per node).  params:
+ * device blob of gnn_blob_len(0) floats (the zero-round layout above).
+ * workspace: >= lbm_workspace_bytes(LBM_WS_SIMPLE, ...) bytes.  fb as for
+ * lbm_step_gnn (NULL = no gate). */
+int lbm_step_simple(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                    const float *params, const lbm_fallback *fb, void *workspace,
+                    size_t ws_bytes, void *stream);
+/* The same collision alone (no streaming) on a batch of pre-collision states
+ * [batch][ny][9][nx], tau: device float[batch]; head_out NULL or
+ * [batch][ny][nx][10]. */
+int simple_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
+                   const float *tau, const float *params, float *head_out, void *workspace,
+                   size_t ws_bytes, void *stream);
+
 /* Eq. 4 with N = batch*nx*ny nodes: loss = scale/N * sum (a - b)^2 over all
  * nodes and the 9 populations, accumulated in FP64 into *loss (device
  * double); grad_a (NULL or like a) receives d loss / d a in FP32.
@@ -226,7 +245,8 @@ enum {
   LBM_WS_GNN_FORWARD = 2,
   LBM_WS_GNN_SAVED = 3,
   LBM_WS_GNN_BACKWARD = 4,
-  LBM_WS_MSE = 5
+  LBM_WS_MSE = 5,
+  LBM_WS_SIMPLE = 6
 };
 /* Bytes needed by operation `op` for the given sizes (0 if op is unknown). */
 size_t lbm_workspace_bytes(int op, int batch, int nx, int ny, int n_rounds);

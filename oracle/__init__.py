@@ -73,6 +73,10 @@ def lib():
         L.orc_project.argtypes = [pd, pd]
         L.orc_gnn_collide.argtypes = [pd, pd, i, i, i, pd, pd, i, i, pd]
         L.orc_gnn_collide.restype = i
+        L.orc_gnn_collide_act.argtypes = [pd, pd, i, i, i, pd, pd, i, i, i, pd]
+        L.orc_gnn_collide_act.restype = i
+        L.orc_gnn_backward_act.argtypes = [pd, pd, i, i, i, pd, pd, i, i, i, pd]
+        L.orc_gnn_backward_act.restype = i
         L.orc_gnn_collide_nodes.argtypes = [pd, i, i, d, pd, i, i,
                                             P(ctypes.c_long), i, pd, pd]
         L.orc_gnn_collide_nodes.restype = i
@@ -222,9 +226,10 @@ def project(v) -> np.ndarray:
 
 
 def gnn_collide(f, tau, blob, rounds: int = 2, mode: int = 0,
-                want_z: bool = False):
+                want_z: bool = False, act: int = 0):
     """GNN-corrected collision (Eq. 3) of pre-collision f ([9,ny,nx] or
-    [B,9,ny,nx]).  mode 0 = FP64, 1 = BF16 storage emulation."""
+    [B,9,ny,nx]).  mode 0 = FP64, 1 = BF16 storage emulation; act 0 = GELU,
+    1 = ReLU (with rounds = 0: the per-node network of the paper's Fig. 2)."""
     f = _f64(f)
     single = f.ndim == 3
     if single:
@@ -235,8 +240,8 @@ def gnn_collide(f, tau, blob, rounds: int = 2, mode: int = 0,
     assert blob.size == blob_len(rounds)
     out = np.empty_like(f)
     z = np.zeros((B, ny, nx, NOUT)) if want_z else None
-    rc = lib().orc_gnn_collide(_p(f), _p(out), B, nx, ny, _p(tau), _p(blob),
-                               rounds, mode, _p(z) if want_z else None)
+    rc = lib().orc_gnn_collide_act(_p(f), _p(out), B, nx, ny, _p(tau), _p(blob),
+                                   rounds, mode, act, _p(z) if want_z else None)
     if rc:
         raise MemoryError("oracle forward could not allocate")
     if single:
@@ -264,7 +269,7 @@ def gnn_collide_nodes(f, tau: float, blob, nodes, rounds: int = 2,
     return fs, z
 
 
-def gnn_backward(f, G, tau, blob, rounds: int = 2, mode: int = 0):
+def gnn_backward(f, G, tau, blob, rounds: int = 2, mode: int = 0, act: int = 0):
     """dL/dparams given G = dL/df* at the forward output."""
     f = _f64(f)
     G = _f64(G)
@@ -274,8 +279,8 @@ def gnn_backward(f, G, tau, blob, rounds: int = 2, mode: int = 0):
     tau = _f64(np.broadcast_to(np.asarray(tau, dtype=np.float64), (B,)))
     blob = _f64(blob)
     grad = np.zeros(param_count(rounds))
-    rc = lib().orc_gnn_backward(_p(f), _p(G), B, nx, ny, _p(tau), _p(blob),
-                                rounds, mode, _p(grad))
+    rc = lib().orc_gnn_backward_act(_p(f), _p(G), B, nx, ny, _p(tau), _p(blob),
+                                    rounds, mode, act, _p(grad))
     if rc:
         raise MemoryError("oracle backward could not allocate")
     return grad

@@ -88,7 +88,16 @@ typedef struct {
   const double *Wh, *bh, *mu, *sigma;
   double sdelta;
   int R;
+  int act; /* 0: GELU (tanh form), 1: ReLU (the per-node network of Fig. 2) */
 } net_t;
+
+static double act_fn(const net_t *n, double x) {
+  return n->act ? (x > 0.0 ? x : 0.0) : gelu(x);
+}
+
+static double act_grad_fn(const net_t *n, double x) {
+  return n->act ? (x > 0.0 ? 1.0 : 0.0) : gelu_grad(x);
+}
 
 /* Offsets of every tensor in the blob; the same walk sizes the gradient. */
 typedef struct {
@@ -152,6 +161,7 @@ static void bind(const double *blob, int R, int mode, double *store,
   n->Wh = store + L.Wh; n->bh = store + L.bh;
   n->mu = store + L.mu; n->sigma = store + L.sigma;
   n->sdelta = store[L.sdelta];
+  n->act = 0;
 }
 
 /* out = Wm in + b, Wm row-major [nout][nin]. */
@@ -218,9 +228,9 @@ static void encode(const double *x, const net_t *net, int mode, double *e1,
                    double *h0) {
   double p[HID];
   dense(net->W1, net->b1, x, NFEAT, HID, p);
-  for (int c = 0; c < HID; ++c) e1[c] = rnd(gelu(p[c]), mode);
+  for (int c = 0; c < HID; ++c) e1[c] = rnd(act_fn(net, p[c]), mode);
   dense(net->W2, net->b2, e1, HID, HID, p);
-  for (int c = 0; c < HID; ++c) h0[c] = rnd(gelu(p[c]), mode);
+  for (int c = 0; c < HID; ++c) h0[c] = rnd(act_fn(net, p[c]), mode);
 }
 
 /* One message-passing round for a receiver with state hn and neighbour
@@ -237,13 +247,13 @@ static void mp_node(const double *hn, const double *const hj[9],
     in[2 * HID] = EX[d];
     in[2 * HID + 1] = EY[d];
     dense(net->We[r], net->be[r], in, EDGE_IN, HID, q);
-    for (int c = 0; c < HID; ++c) agg[c] += gelu(q[c]);
+    for (int c = 0; c < HID; ++c) agg[c] += act_fn(net, q[c]);
   }
   for (int c = 0; c < HID; ++c) agg[c] = rnd(agg[c], mode);
   memcpy(cat, hn, HID * sizeof(double));
   memcpy(cat + HID, agg, HID * sizeof(double));
   dense(net->Wn[r], net->bn[r], cat, NODE_IN, HID, p);
-  for (int c = 0; c < HID; ++c) hout[c] = rnd(gelu(p[c]), mode);
+  for (int c = 0; c < HID; ++c) hout[c] = rnd(act_fn(net, p[c]), mode);
 }
 
 /* Orthogonal projector onto null(M), M = [1; e_x; e_y] (3 x 9):
@@ -376,6 +386,21 @@ static int forward(const double *f, int batch, int nx, int ny,
   return 0;
 }
 
+int orc_gnn_collide_act(const double *f, double *fstar, int batch, int nx,
+                        int ny, const double *tau, const double *blob, int R,
+                        int mode, int act, double *zout) {
+  if (R < 0 || R > MAXR) return -1;
+  double *store = (double *)malloc(layout(R).total * sizeof(double));
+  net_t net;
+  bind(blob, R, mode, store, &net);
+  net.act = act;
+  acts_t a;
+  int rc = forward(f, batch, nx, ny, tau, &net, mode, fstar, zout, &a);
+  if (rc == 0) acts_free(&a);
+  free(store);
+  return rc;
+}
+
 int orc_gnn_collide(const double *f, double *fstar, int batch, int nx, int ny,
                     const double *tau, const double *blob, int R, int mode,
                     double *zout) {
@@ -443,14 +468,31 @@ int orc_gnn_collide_nodes(const double *f, int nx, int ny, double tau,
 /* Gradient of a scalar loss with respect to the trainable parameters, given
  * its gradient G = dL/df* ([batch][9][ny][nx]) at the forward's output.
  * grad: [orc_gnn_param_count(R)], overwritten. */
+static int backward_impl(const double *f, const double *G, int batch, int nx,
+                         int ny, const double *tau, const double *blob, int R,
+                         int mode, int act, double *grad);
+
 int orc_gnn_backward(const double *f, const double *G, int batch, int nx,
                      int ny, const double *tau, const double *blob, int R,
                      int mode, double *grad) {
+  return backward_impl(f, G, batch, nx, ny, tau, blob, R, mode, 0, grad);
+}
+
+int orc_gnn_backward_act(const double *f, const double *G, int batch, int nx,
+                         int ny, const double *tau, const double *blob, int R,
+                         int mode, int act, double *grad) {
+  return backward_impl(f, G, batch, nx, ny, tau, blob, R, mode, act, grad);
+}
+
+static int backward_impl(const double *f, const double *G, int batch, int nx,
+                         int ny, const double *tau, const double *blob, int R,
+                         int mode, int act, double *grad) {
   if (R < 0 || R > MAXR) return -1;
   layout_t L = layout(R);
   double *store = (double *)malloc(L.total * sizeof(double));
   net_t net;
   bind(blob, R, mode, store, &net);
+  net.act = act;
   size_t plane = (size_t)nx * ny, N = (size_t)batch * plane;
   double *fstar = (double *)malloc(N * 9 * sizeof(double));
   acts_t a;
@@ -500,7 +542,7 @@ int orc_gnn_backward(const double *f, const double *G, int batch, int nx,
           memcpy(cat + HID, agg + g * HID, HID * sizeof(double));
           dense(net.Wn[r], net.bn[r], cat, NODE_IN, HID, p);
           for (int c = 0; c < HID; ++c)
-            dp[c] = dh[g * HID + c] * gelu_grad(p[c]);
+            dp[c] = dh[g * HID + c] * act_grad_fn(&net, p[c]);
           outer_acc(grad + L.Wn[r], grad + L.bn[r], dp, cat, NODE_IN, HID);
           memset(dcat, 0, sizeof(dcat));
           dense_t(net.Wn[r], dp, NODE_IN, HID, dcat);
@@ -514,7 +556,7 @@ int orc_gnn_backward(const double *f, const double *G, int batch, int nx,
             in[2 * HID + 1] = EY[d];
             dense(net.We[r], net.be[r], in, EDGE_IN, HID, q);
             for (int c = 0; c < HID; ++c)
-              dq[c] = dcat[HID + c] * gelu_grad(q[c]);
+              dq[c] = dcat[HID + c] * act_grad_fn(&net, q[c]);
             outer_acc(grad + L.We[r], grad + L.be[r], dq, in, EDGE_IN, HID);
             memset(din, 0, sizeof(din));
             dense_t(net.We[r], dq, EDGE_IN, HID, din);
@@ -532,12 +574,12 @@ int orc_gnn_backward(const double *f, const double *G, int batch, int nx,
     double p[HID], dp[HID], de1[HID];
     const double *x = a.x + g * NFEAT, *e1 = a.e1 + g * HID;
     dense(net.W2, net.b2, e1, HID, HID, p);
-    for (int c = 0; c < HID; ++c) dp[c] = dh[g * HID + c] * gelu_grad(p[c]);
+    for (int c = 0; c < HID; ++c) dp[c] = dh[g * HID + c] * act_grad_fn(&net, p[c]);
     outer_acc(grad + L.W2, grad + L.b2, dp, e1, HID, HID);
     memset(de1, 0, sizeof(de1));
     dense_t(net.W2, dp, HID, HID, de1);
     dense(net.W1, net.b1, x, NFEAT, HID, p);
-    for (int c = 0; c < HID; ++c) dp[c] = de1[c] * gelu_grad(p[c]);
+    for (int c = 0; c < HID; ++c) dp[c] = de1[c] * act_grad_fn(&net, p[c]);
     outer_acc(grad + L.W1, grad + L.b1, dp, x, NFEAT, HID);
   }
   free(dh);

@@ -18,12 +18,14 @@ LBM_WS_GNN_FORWARD = 2
 LBM_WS_GNN_SAVED = 3
 LBM_WS_GNN_BACKWARD = 4
 LBM_WS_MSE = 5
+LBM_WS_SIMPLE = 6
 
 EXPORTS = [
     "lbm_last_error", "lbm_init", "lbm_init_f64", "lbm_step_bgk", "lbm_step_bgk_f64",
     "lbm_stream", "lbm_init_ce", "lbm_init_ce_f64",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
     "lbm_step_gnn", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
+    "lbm_step_simple", "simple_forward",
     "lbm_workspace_bytes",
 ]
 
@@ -76,6 +78,8 @@ def load(path: str = LIB_PATH):
         "gnn_backward": ([vp, vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
         "gnn_mse": ([vp, vp, i, i, i, d, vp, vp, vp, sz, vp], i),
         "gnn_adam": ([vp, vp, vp, vp, sz, f, f, f, f, i, vp], i),
+        "lbm_step_simple": ([vp, vp, i, i, f, vp, ctypes.POINTER(LbmFallback), vp, sz, vp], i),
+        "simple_forward": ([vp, vp, i, i, i, vp, vp, vp, vp, sz, vp], i),
         "lbm_workspace_bytes": ([i, i, i, i, i], sz),
     }
     for name, (args, res) in sig.items():

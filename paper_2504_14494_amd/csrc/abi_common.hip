@@ -62,6 +62,8 @@ extern "C" size_t lbm_workspace_bytes(int op, int batch, int nx, int ny, int n_r
       return gnn::saved_bytes(batch, nx, ny, n_rounds);
     case LBM_WS_GNN_BACKWARD:
       return gnn::backward_workspace_bytes(batch, nx, ny, n_rounds);
+    case LBM_WS_SIMPLE:
+      return gnn::simple_scratch().total;
     default:
       return 0;
   }

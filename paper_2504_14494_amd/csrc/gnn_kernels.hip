@@ -625,11 +625,11 @@ static int device_cus() {
 static inline void *at(void *base, size_t off) { return (uint8_t *)base + off; }
 
 extern "C" size_t gnn_param_count(int n_rounds) {
-  if (n_rounds < 1 || n_rounds > MAX_ROUNDS) return 0;
+  if (n_rounds < 0 || n_rounds > MAX_ROUNDS) return 0;
   return blob_layout(n_rounds).nparam;
 }
 extern "C" size_t gnn_blob_len(int n_rounds) {
-  if (n_rounds < 1 || n_rounds > MAX_ROUNDS) return 0;
+  if (n_rounds < 0 || n_rounds > MAX_ROUNDS) return 0;
   return blob_layout(n_rounds).total;
 }
 
@@ -727,6 +727,31 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
 
 }  // namespace gnn
 
+namespace gnn {
+
+// The per-step fallback gate after a corrected step whose workgroups left
+// nparts FP64 mass partials and flag words: decide, recompute with plain BGK
+// if tripped (the kernel exits at once otherwise), and update the mass.
+int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                const lbm_fallback *fb, int nparts, void *pmass, void *pflag, void *pmass2,
+                void *ctrl, hipStream_t s) {
+  double nodes = (double)nx * ny;
+  hipLaunchKernelGGL(gate_decide_kernel, dim3(1), dim3(kThreads), 0, s, (const double *)pmass,
+                     (const unsigned *)pflag, nparts, nodes, fb->drift_threshold, fb->flags,
+                     fb->n_fallback, fb->mass, (unsigned *)ctrl);
+  if (int rc = launch_check("gate_decide_kernel")) return rc;
+  long long fbn = ((long long)nx * ny + kThreads - 1) / kThreads;
+  int fbb = (int)(fbn < kMaxGnnBlocks ? fbn : kMaxGnnBlocks);
+  hipLaunchKernelGGL(gate_fallback_kernel, dim3(fbb), dim3(kThreads), 0, s, g_src, g_dst, nx, ny,
+                     1.0f / tau, (const unsigned *)ctrl, (double *)pmass2);
+  if (int rc = launch_check("gate_fallback_kernel")) return rc;
+  hipLaunchKernelGGL(gate_mass_kernel, dim3(1), dim3(kThreads), 0, s, (const double *)pmass2,
+                     fbb, nodes, (const unsigned *)ctrl, fb->mass);
+  return launch_check("gate_mass_kernel");
+}
+
+}  // namespace gnn
+
 static int check_gnn_common(const char *who, int batch, int nx, int ny, const float *params,
                             int R) {
   if (!params) return fail(LBM_EINVAL, "%s: null parameters", who);
@@ -780,20 +805,6 @@ extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, fl
     return rc;
   if (!fb) return LBM_OK;
   const ForwardScratch W = forward_scratch((long long)nx * ny);
-  double nodes = (double)nx * ny;
-  unsigned *ctrl = (unsigned *)at(workspace, W.ctrl);
-  hipLaunchKernelGGL(gate_decide_kernel, dim3(1), dim3(kThreads), 0, s,
-                     (const double *)at(workspace, W.pmass),
-                     (const unsigned *)at(workspace, W.pflag), nparts, nodes,
-                     fb->drift_threshold, fb->flags, fb->n_fallback, fb->mass, ctrl);
-  if (int rc = launch_check("gate_decide_kernel")) return rc;
-  long long fbn = ((long long)nx * ny + kThreads - 1) / kThreads;
-  int fbb = (int)(fbn < kMaxGnnBlocks ? fbn : kMaxGnnBlocks);
-  double *pm2 = (double *)at(workspace, W.pmass2);
-  hipLaunchKernelGGL(gate_fallback_kernel, dim3(fbb), dim3(kThreads), 0, s, g_src, g_dst, nx, ny,
-                     1.0f / tau, ctrl, pm2);
-  if (int rc = launch_check("gate_fallback_kernel")) return rc;
-  hipLaunchKernelGGL(gate_mass_kernel, dim3(1), dim3(kThreads), 0, s, pm2, fbb, nodes, ctrl,
-                     fb->mass);
-  return launch_check("gate_mass_kernel");
+  return launch_gate(g_src, g_dst, nx, ny, tau, fb, nparts, at(workspace, W.pmass),
+                     at(workspace, W.pflag), at(workspace, W.pmass2), at(workspace, W.ctrl), s);
 }

@@ -107,6 +107,24 @@ inline size_t forward_workspace_bytes(int batch, int nx, int ny, int R) {
   return forward_scratch((long long)batch * nx * ny).total;
 }
 
+// Scratch of the fused per-node step: packed weights, per-workgroup partials
+// of the corrected collision and of the fallback step, control words.
+struct SimpleScratch {
+  size_t pack, pmass, pflag, pmass2, ctrl, total;
+};
+
+inline SimpleScratch simple_scratch() {
+  SimpleScratch S{};
+  size_t o = 0;
+  S.pack = o; o += kPackBytes;
+  S.pmass = o; o += align256(kMaxGnnBlocks * sizeof(double));
+  S.pflag = o; o += align256(kMaxGnnBlocks * sizeof(unsigned));
+  S.pmass2 = o; o += align256(kMaxGnnBlocks * sizeof(double));
+  S.ctrl = o; o += 256;
+  S.total = o;
+  return S;
+}
+
 inline size_t step_workspace_bytes(int nx, int ny, int R) {
   return forward_workspace_bytes(1, nx, ny, R);
 }

@@ -17,7 +17,7 @@ from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
            "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
-           "GnnMse"]
+           "GnnMse", "simple_forward", "lbm_step_simple"]
 
 
 def gnn_param_count(rounds: int = 2) -> int:
@@ -115,6 +115,51 @@ def lbm_step_gnn(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.T
     return dst
 
 
+def simple_forward(g_pre: torch.Tensor, tau: torch.Tensor, blob: torch.Tensor,
+                   want_z: bool = False, ws: Workspace = None):
+    """The per-node (Fig. 2) corrected collision of a batch of pre-collision
+    states, no streaming.  blob: zero-round layout.  Returns (g_post, z)."""
+    single = g_pre.dim() == 3
+    if single:
+        g_pre = g_pre.unsqueeze(0)
+    _need(g_pre, torch.float32, "g_pre")
+    B, nx, ny = _batch_dims(g_pre)
+    _need(tau, torch.float32, "tau")
+    if tau.numel() != B:
+        raise ValueError("tau needs one value per lattice")
+    _check_blob(blob, 0)
+    out = torch.empty_like(g_pre)
+    z = torch.empty((B, ny, nx, 10), dtype=torch.float32, device=g_pre.device) if want_z else None
+    L = _lib.load()
+    buf = (ws or _ws).get(L.lbm_workspace_bytes(_lib.LBM_WS_SIMPLE, B, nx, ny, 0))
+    rc = L.simple_forward(_ptr(g_pre), _ptr(out), B, nx, ny, _ptr(tau), _ptr(blob), _ptr(z),
+                          _ptr(buf), buf.numel(), _stream())
+    check(rc, "simple_forward")
+    if single:
+        out = out[0]
+        z = z[0] if z is not None else None
+    return out, z
+
+
+def lbm_step_simple(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.Tensor,
+                    fallback: Fallback = None, ws: Workspace = None):
+    """One step with the per-node (Fig. 2) corrected collision fused into the
+    pull step; blob: zero-round layout."""
+    _need(src, torch.float32, "src")
+    _need(dst, torch.float32, "dst")
+    if src.dim() != 3 or src.shape[1] != 9 or src.shape != dst.shape:
+        raise ValueError("src and dst must both be [ny, 9, nx]")
+    _check_blob(blob, 0)
+    ny, nx = int(src.shape[0]), int(src.shape[2])
+    L = _lib.load()
+    buf = (ws or _ws).get(L.lbm_workspace_bytes(_lib.LBM_WS_SIMPLE, 1, nx, ny, 0))
+    fb = ctypes.byref(fallback.struct()) if fallback is not None else None
+    rc = L.lbm_step_simple(_ptr(src), _ptr(dst), nx, ny, float(tau), _ptr(blob), fb, _ptr(buf),
+                           buf.numel(), _stream())
+    check(rc, "lbm_step_simple")
+    return dst
+
+
 class GnnLattice(Lattice):
     """A/B buffers of one periodic lattice stepped with the plain BGK or the
     GNN-corrected collision, with the per-step fallback gate."""
@@ -157,9 +202,14 @@ class GnnLattice(Lattice):
         return self
 
     def step_gnn(self, tau: float, n: int = 1, gate: bool = True):
+        """Corrected steps: message passing for rounds >= 1, the fused
+        per-node network of Fig. 2 for rounds == 0."""
+        fb = self.fallback if gate else None
         for _ in range(n):
-            lbm_step_gnn(self.a, self.b, tau, self.blob, self.rounds,
-                         self.fallback if gate else None, self.ws)
+            if self.rounds == 0:
+                lbm_step_simple(self.a, self.b, tau, self.blob, fb, self.ws)
+            else:
+                lbm_step_gnn(self.a, self.b, tau, self.blob, self.rounds, fb, self.ws)
             self.a, self.b = self.b, self.a
             self.steps += 1
         return self

@@ -224,7 +224,7 @@ def test_backward_matches_central_differences(orc):
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), name
 
 
-def _torch_net(f, tau, blob, rounds=R):
+def _torch_net(f, tau, blob, rounds=R, act="gelu"):
     """The same network written with torch CPU ops (float64), used as a third,
     independently written checker of the oracle forward and backward."""
     offs = inputs.blob_offsets(rounds)
@@ -238,7 +238,7 @@ def _torch_net(f, tau, blob, rounds=R):
     feat = torch.cat([f - w[None, :, None, None], (rho - 1)[:, None],
                       ux[:, None], uy[:, None]], 1).permute(0, 2, 3, 1)
     x = (feat - P["mu"]) / P["sigma"]
-    g = lambda t: F.gelu(t, approximate="tanh")
+    g = (lambda t: F.gelu(t, approximate="tanh")) if act == "gelu" else F.relu
     h = g(F.linear(g(F.linear(x, P["W1"], P["b1"])), P["W2"], P["b2"]))
     for r in range(rounds):
         agg = 0
@@ -274,6 +274,26 @@ def test_torch_composition_agrees(orc):
     assert np.abs(out - out_t.detach().numpy()).max() < 1e-13
     grad = orc.gnn_backward(f, G, tau, blob)
     gt = bt.grad.numpy()[:orc.param_count(R)]
+    assert np.abs(grad - gt).max() <= 1e-10 * np.abs(gt).max()
+
+
+def test_per_node_relu_network_agrees_with_torch(orc):
+    """The paper's Fig. 2 network: no message passing (0 rounds), ReLU."""
+    B, ny, nx = 2, 3, 4
+    f = _state(orc, (B, 9, ny, nx), 23)
+    G = np.random.default_rng(24).standard_normal(f.shape)
+    tau = np.array([0.65, 0.9])
+    blob = inputs.gnn_blob(21, 0, s_delta=0.2).astype(np.float64)
+    assert blob.size == orc.blob_len(0) and orc.param_count(0) == 5642
+    bt = torch.tensor(blob, requires_grad=True)
+    out_t = _torch_net(torch.tensor(f), torch.tensor(tau), bt, rounds=0, act="relu")
+    (out_t * torch.tensor(G)).sum().backward()
+    out = orc.gnn_collide(f, tau, blob, rounds=0, act=1)
+    assert np.abs(out - out_t.detach().numpy()).max() < 1e-13
+    # the GELU network with 0 rounds is a different function
+    assert np.abs(orc.gnn_collide(f, tau, blob, rounds=0, act=0) - out).max() > 1e-6
+    grad = orc.gnn_backward(f, G, tau, blob, rounds=0, act=1)
+    gt = bt.grad.numpy()[:orc.param_count(0)]
     assert np.abs(grad - gt).max() <= 1e-10 * np.abs(gt).max()
 
 
