@@ -13,6 +13,8 @@ rocprofv3 counters).  Beside it:
                its 128^2 rollout against plain BGK at 128^2 and 256^2, all
                measured against a restricted FP64 512^2 run, with the time each
                needs (measured and projected from the large-lattice MLUPS);
+               and the paper's resolution study (observed order, Eq. 6) and
+               Reynolds-number sweep, trained network beside plain BGK;
   cpu_baseline the FP64 CPU oracle timed on the host on a bounded sample.
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -140,22 +142,50 @@ GNN_MAC_PER_NODE = 12 * 64 + 64 * 64 + 2 * (64 * 64 + 64 * 64 + 64 * 128) + 64 *
 GNN_GELU_PER_NODE = 128 + 2 * (8 * 64 + 64)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # FP32 VALU without packed math: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
-# A GELU costs 5 full-rate ops and 2 quarter-rate transcendentals = 13 slots.
-GELU_PEAK_PER_S = 256 * 64 * 2.4e9 / 13
+# A GELU is 5 full-rate ops (x*x, fma, mul, add, mul) and 2 transcendentals
+# (v_exp_f32, v_rcp_f32) that each occupy the VALU for two issue slots
+# (8 cycles per wave64; the GELU throughput kernel measures the result):
+# 9 slots.
+GELU_SLOTS = 5 + 2 * 2
+GELU_PEAK_PER_S = 256 * 64 * 2.4e9 / GELU_SLOTS
 
 
-def gnn_roofline(ms_per_step, nodes):
+def gelu_ceiling_leg(blocks=8192, iters=1024, reps=5):
+    """Measured GELU rate of the VALU: the network's GELU on independent
+    register chains, no memory traffic."""
+    import torch
+    from paper_2504_14494_amd import gnn
+    out = torch.empty(blocks * 256, device="cuda")
+    gnn.gnn_gelu_rate(out, 16)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        gnn.gnn_gelu_rate(out, iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    if not torch.isfinite(out).all().item():
+        raise RuntimeError("GELU throughput kernel produced non-finite values")
+    return 8.0 * blocks * 256 * iters / (ms * 1e-3)
+
+
+def gnn_roofline(ms_per_step, nodes, gelu_measured=None):
     """MFMA and VALU (GELU) rooflines of the corrected step; counters of the
     committed rocprofv3 summary when it matches the kernel source."""
     sec = ms_per_step * 1e-3
     mfma_tf = 2.0 * GNN_MAC_PER_NODE * nodes / sec / 1e12
     gelu_rate = GNN_GELU_PER_NODE * nodes / sec
+    alu = {"bound": "alu", "achieved": round(gelu_rate / 1e12, 3),
+           "peak": round(GELU_PEAK_PER_S / 1e12, 3), "unit": "T GELU/s",
+           "frac": round(gelu_rate / GELU_PEAK_PER_S, 4), "slots_per_gelu": GELU_SLOTS}
+    if gelu_measured:
+        alu["gelu_ceiling_measured"] = round(gelu_measured / 1e12, 3)
+        alu["frac_of_measured"] = round(gelu_rate / gelu_measured, 4)
     r = {"roofline_mfma": {"bound": "mfma", "achieved": round(mfma_tf, 1),
                            "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(mfma_tf / MFMA_BF16_PEAK_TFLOPS, 4)},
-         "roofline_alu": {"bound": "alu", "achieved": round(gelu_rate / 1e12, 3),
-                          "peak": round(GELU_PEAK_PER_S / 1e12, 3), "unit": "T GELU/s",
-                          "frac": round(gelu_rate / GELU_PEAK_PER_S, 4)}}
+         "roofline_alu": alu}
     t = _committed(GNN_PMC_FILE, gnn_src_hash())
     r["counters"] = None if t is None else t.get("utilisation")
     return r
@@ -171,7 +201,40 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
            "heldout_loss_over_bgk": rep["heldout_rel_loss_after"]}
     out.update(experiments.fixed_error_report(tr.blob, mlups_bgk=mlups_bgk,
                                               mlups_gnn=mlups_gnn))
+    out["studies"] = studies_leg(tr.blob)
     return out
+
+
+def _compact_res(rep):
+    return {"alpha": [round(a, 3) for a in rep["alpha"]],
+            "vel_err": [float(f"{r['vel_err']:.4g}") for r in rep["rows"]],
+            "fallback_steps": [r.get("fallback_steps", 0) for r in rep["rows"]]}
+
+
+def studies_leg(blob):
+    """The paper's Taylor-Green studies with the trained network beside
+    plain BGK: the observed order of Eq. 6 over 32/64/128 (Re = 100) in
+    diffusive and acoustic scaling, and the 64^2 Reynolds-number sweep."""
+    from paper_2504_14494_amd import experiments
+    res = {}
+    for scaling in ("diffusive", "acoustic"):
+        res[scaling] = {
+            "bgk": _compact_res(experiments.resolution_study(None, scaling=scaling)),
+            "bgk_fp64": _compact_res(experiments.resolution_study(None, scaling=scaling,
+                                                                  fp64=True)),
+            "gnn": _compact_res(experiments.resolution_study(blob, scaling=scaling))}
+    stab = []
+    # the paper's Reynolds numbers at u0 = 0.04, then u0 = 0.2, where plain
+    # BGK does break down on this lattice
+    for u0, res_list in ((0.04, (100, 200, 400, 800, 1600, 3200)), (0.2, (12800, 51200))):
+        sw = experiments.stability_sweep(blob, u0=u0, re_list=res_list)
+        stab += [{"u0": u0, "re": r["re"], "tau": round(r["tau"], 6),
+                  "bgk_first_bad_step": r["bgk"]["first_bad_step"],
+                  "gnn_first_bad_step": r["gnn"]["first_bad_step"],
+                  "gnn_fallback_steps": r["gnn"]["fallback_steps"],
+                  "bgk_energy_err": float(f"{r['bgk']['energy_err']:.4g}"),
+                  "gnn_energy_err": float(f"{r['gnn']['energy_err']:.4g}")} for r in sw["runs"]]
+    return {"resolution_re100": res, "stability_64": {"steps": 20000, "runs": stab}}
 
 
 def simple_leg(n, steps, warmup, ms_bgk):
@@ -294,7 +357,7 @@ def main():
             g = gnn_leg(2048, args.gnn_steps, 3)
             g["bgk_mlups_same_gpu"] = out["value"]
             g["step_over_bgk_step"] = round(out["value"] / g["mlups"], 1)
-            g.update(gnn_roofline(g["ms_per_step"], 2048 * 2048))
+            g.update(gnn_roofline(g["ms_per_step"], 2048 * 2048, gelu_ceiling_leg()))
             out["gnn"] = g
         except Exception as e:  # reported, never hidden
             out["gnn"] = {"error": repr(e)}

@@ -134,6 +134,15 @@ int lbm_restrict(const double *g_fine, int nxf, int nyf, int factor,
 /* Plain copy of n floats (bandwidth reference for the BGK kernel). */
 int lbm_copy(const float *src, float *dst, size_t n, void *stream);
 
+/* VALU throughput reference for the corrected step: each of nblocks x 256
+ * threads applies the network's GELU (tanh form, evaluated as
+ * x / (1 + 2^(x (A + B x^2)))) `iters` times to eight independent register
+ * values and writes their sum to out[thread].  `out` is a device array of
+ * nblocks * 256 floats owned by the caller.  Rejects nblocks or iters outside
+ * [1, 2^20] with LBM_EINVAL.  Time it on `stream` to obtain the GELU rate the
+ * message-passing rounds are bound by: 8 * 256 * nblocks * iters GELUs. */
+int gnn_gelu_rate(float *out, int nblocks, int iters, void *stream);
+
 /* ------------------------------------------------------------------------ *
  * GNN-corrected collision (Eq. 3)                                          *
  * ------------------------------------------------------------------------ */

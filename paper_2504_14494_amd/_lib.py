@@ -25,7 +25,7 @@ EXPORTS = [
     "lbm_stream", "lbm_init_ce", "lbm_init_ce_f64",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
     "lbm_step_gnn", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
-    "lbm_step_simple", "simple_forward",
+    "lbm_step_simple", "simple_forward", "gnn_gelu_rate",
     "lbm_workspace_bytes",
 ]
 
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH):
         "lbm_moments": ([vp, i, i, vp, vp, vp, ctypes.POINTER(LbmTgv), vp, vp, sz, vp], i),
         "lbm_restrict": ([vp, i, i, i, d, d, i, i, vp, vp], i),
         "lbm_copy": ([vp, vp, sz, vp], i),
+        "gnn_gelu_rate": ([vp, i, i, vp], i),
         "gnn_param_count": ([i], sz),
         "gnn_blob_len": ([i], sz),
         "lbm_step_gnn": ([vp, vp, i, i, f, vp, i, ctypes.POINTER(LbmFallback), vp, sz, vp], i),

@@ -1,7 +1,9 @@
 """Accuracy experiments on the GPU: plain BGK against the GNN-corrected
-collision at equal Taylor-Green velocity error (paper: "Taylor-Green Vortex
-Validation" and "Resolution Study"; velocity L2 error as read in R5 of the
-design notes).
+collision on the paper's Taylor-Green studies ("Taylor-Green Vortex
+Validation", "Resolution Study" with the convergence rate of Eq. 6,
+"Reynolds Number Study"), and at equal velocity error.  The velocity error
+is the relative L2 norm over all nodes and both components; the energy is
+half the sum of |u|^2 over the nodes.
 
 The reference is an FP64 BGK run on a fine lattice (n_fine), restricted to
 each coarse lattice at equal physical time (acoustic scaling: one coarse
@@ -169,3 +171,130 @@ def long_rollout(blob, rounds=2, n=2048, u0=0.05, re=1e4, steps=20000, sample_ev
     return {"n": n, "u0": u0, "re": re, "tau": tau, "steps": steps,
             "mlups": n * n * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
             "samples": rows}
+
+
+def _analytic(n, u0, tau32, t):
+    """Decaying Taylor-Green field of a run whose relaxation time is tau32:
+    nu = (tau - 1/2) / 3, amplitude factor exp(-2 nu k^2 t)."""
+    k = 2.0 * math.pi / n
+    return (u0, k, k, 0.0, 0.0, (tau32 - 0.5) / 3.0, float(t))
+
+
+def tgv_state_errors(g32, n, u0, tau32, t):
+    """Velocity and energy errors of a lattice state against the analytic
+    Taylor-Green field at step t, plus its smallest population and number of
+    negative populations (all from the FP64 sums of lbm_moments)."""
+    _, _, _, sums = lbm.lbm_moments(g32, analytic=_analytic(n, u0, tau32, t))
+    s = sums.cpu().numpy()
+    e_a = 0.5 * s[5]
+    finite = bool(np.isfinite(s).all())
+    return {"vel_err": float(math.sqrt(s[4] / s[5])) if finite else float("nan"),
+            "energy_err": float(abs(s[3] - e_a) / e_a) if finite else float("nan"),
+            "energy": float(s[3]), "min_f": float(s[6]), "n_negative": int(s[7]),
+            "finite": finite}
+
+
+def _lattice(n, u0, tau32, blob, rounds, fp64=False):
+    if fp64:
+        return lbm.Lattice(n, n, dtype=torch.float64).init_ce(
+            *tgv_fields(n, u0, (0.0, 0.0)), tau32)
+    fields = tgv_fields(n, u0, (0.0, 0.0), np.float32)
+    if blob is None:
+        return lbm.Lattice(n, n).init_ce(*fields, tau32)
+    return gnn.GnnLattice(n, n, blob, rounds).init_ce(*fields, tau32)
+
+
+def _fp32_view(lat, tau):
+    """FP32 populations with the lattice's density and velocity (an FP64
+    lattice goes through the factor-1 restriction, which keeps rho and u)."""
+    if lat.a.dtype == torch.float32:
+        return lat.a
+    return lbm.lbm_restrict(lat.a, 1, tau, tau, pull=False, unstream=False)
+
+
+def _advance(lat, blob, tau32, k):
+    if blob is None:
+        lat.step_bgk(tau32, k)
+    else:
+        lat.step_gnn(tau32, k)
+
+
+def resolution_study(blob=None, rounds=2, re=100.0, sizes=(32, 64, 128), scaling="diffusive",
+                     u0_ref=0.04, n_ref=64, steps_ref=1000, fp64=False):
+    """Velocity and energy errors against the analytic vortex at equal
+    physical time on several lattices, and the observed order of Eq. 6
+    between neighbouring sizes, alpha = log(E1/E2) / log(h1/h2), h = 1/n.
+
+    scaling "acoustic" keeps u0 (the Mach number) and takes steps in
+    proportion to n; "diffusive" takes u0 = u0_ref n_ref / n (fixed lattice
+    viscosity) and steps in proportion to n^2.  Every run starts on the slow
+    manifold (Chapman-Enskog state with the Taylor-Green pressure).  BGK when
+    blob is None, else the corrected collision with the fallback gate.  With
+    fp64 the BGK runs use FP64 populations, which separates the method's
+    discretisation error from FP32 rounding on long fine-lattice runs."""
+    if scaling not in ("acoustic", "diffusive"):
+        raise ValueError("scaling must be 'acoustic' or 'diffusive'")
+    if fp64 and blob is not None:
+        raise ValueError("the corrected collision runs in FP32 only")
+    rows = []
+    for n in sizes:
+        if scaling == "acoustic":
+            u0, steps = u0_ref, steps_ref * n // n_ref
+        else:
+            u0, steps = u0_ref * n_ref / n, steps_ref * n * n // (n_ref * n_ref)
+        tau32 = float(np.float32(_tau(u0, re, n)))
+        lat = _lattice(n, u0, tau32, blob, rounds, fp64)
+        _advance(lat, blob, tau32, steps)
+        row = {"n": n, "u0": u0, "tau": tau32, "steps": steps}
+        row.update(tgv_state_errors(_fp32_view(lat, tau32), n, u0, tau32, steps))
+        if blob is not None:
+            row["fallback_steps"] = int(lat.n_fallback.item())
+        rows.append(row)
+    alpha = []
+    for a, b in zip(rows, rows[1:]):
+        ok = a["vel_err"] > 0 and b["vel_err"] > 0 and a["finite"] and b["finite"]
+        alpha.append(math.log(a["vel_err"] / b["vel_err"]) / math.log(b["n"] / a["n"])
+                     if ok else float("nan"))
+    return {"re": re, "scaling": scaling, "fp64": fp64, "rows": rows, "alpha": alpha}
+
+
+def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
+                    re_list=(100, 200, 400, 800, 1600, 3200), steps=20000, every=1000):
+    """Taylor-Green runs on an n^2 lattice over a range of Reynolds numbers.
+    Every `every` steps the state is checked: the first check that finds a
+    non-finite or negative population ends the run ("first_bad_step").  The
+    corrected collision runs with the per-step fallback gate, so its first
+    step that fell back to BGK and the number of such steps are reported as
+    well.  Energy and velocity errors are against the analytic decay at the
+    last step reached."""
+    out = []
+    for re in re_list:
+        tau32 = float(np.float32(_tau(u0, re, n)))
+        row = {"re": re, "tau": tau32}
+        for name, b in (("bgk", None), ("gnn", blob)):
+            if name == "gnn" and blob is None:
+                continue
+            lat = _lattice(n, u0, tau32, b, rounds)
+            e0 = tgv_state_errors(lat.a, n, u0, tau32, 0)["energy"]
+            done, first_bad, first_fb, st = 0, None, None, None
+            while done < steps:
+                k = min(every, steps - done)
+                _advance(lat, b, tau32, k)
+                done += k
+                st = tgv_state_errors(lat.a, n, u0, tau32, done)
+                if b is not None and first_fb is None and int(lat.n_fallback.item()) > 0:
+                    first_fb = done
+                if not st["finite"] or st["n_negative"] > 0:
+                    first_bad = done
+                    break
+            r = {"steps_run": done, "first_bad_step": first_bad,
+                 "energy_ratio": st["energy"] / e0 if st["finite"] else float("nan"),
+                 "energy_ratio_analytic": math.exp(-4.0 * (tau32 - 0.5) / 3.0
+                                                   * (2.0 * math.pi / n) ** 2 * done),
+                 "energy_err": st["energy_err"], "vel_err": st["vel_err"]}
+            if b is not None:
+                r["fallback_steps"] = int(lat.n_fallback.item())
+                r["first_fallback_by_step"] = first_fb
+            row[name] = r
+        out.append(row)
+    return {"n": n, "u0": u0, "steps": steps, "check_every": every, "runs": out}

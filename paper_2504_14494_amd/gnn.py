@@ -17,7 +17,7 @@ from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
            "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
-           "GnnMse", "simple_forward", "lbm_step_simple"]
+           "GnnMse", "simple_forward", "lbm_step_simple", "gnn_gelu_rate"]
 
 
 def gnn_param_count(rounds: int = 2) -> int:
@@ -320,3 +320,14 @@ class GnnMse(torch.autograd.Function):
     def backward(ctx, gout):
         (grad,) = ctx.saved_tensors
         return grad * gout, None, None
+
+
+def gnn_gelu_rate(out: torch.Tensor, iters: int):
+    """Runs the GELU throughput kernel: 8 * out.numel() * iters GELUs, with
+    one value per thread written to `out` (a multiple of 256 floats)."""
+    _need(out, torch.float32, "out")
+    if out.numel() % 256 or out.numel() == 0:
+        raise ValueError("out must hold a positive multiple of 256 floats")
+    check(_lib.load().gnn_gelu_rate(_ptr(out), out.numel() // 256, int(iters), _stream()),
+          "gnn_gelu_rate")
+    return out

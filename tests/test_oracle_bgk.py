@@ -246,3 +246,30 @@ def test_chapman_enskog_start_decays_at_the_shear_rate_from_step_one(orc):
         ratio = np.sqrt((vx ** 2 + vy ** 2).sum()) / amp0
         # the lattice shear rate differs from the continuum one by O(k^2)
         assert abs(np.log(ratio) / step + 2 * nu * k * k) < 0.02 * 2 * nu * k * k
+
+
+def _tgv_error(orc, n, u0, re, steps):
+    """Relative L2 velocity error against the decaying vortex after `steps`
+    steps from the Chapman-Enskog start."""
+    nu, tau = inputs.tgv_params(n, u0, re)
+    _, ux, uy = inputs.tgv_velocity(n, n, u0)
+    f = orc.bgk_run(orc.init_ce(inputs.tgv_pressure_density(n, n, u0), ux, uy, tau), tau, steps)
+    _, vx, vy = orc.moments(f)
+    d = math.exp(-2.0 * nu * (2 * np.pi / n) ** 2 * steps)
+    return math.sqrt((((vx - ux * d) ** 2 + (vy - uy * d) ** 2).sum())
+                     / (((ux * d) ** 2 + (uy * d) ** 2).sum()))
+
+
+def test_second_order_convergence_in_diffusive_scaling(orc):
+    """Resolution study (Eq. 6): with the lattice viscosity fixed (u0 in
+    proportion to 1/n, steps to n^2, Re = 100) the BGK error against the
+    incompressible solution falls as h^2; with u0 fixed (acoustic scaling,
+    steps in proportion to n) the O(Ma^2) compressibility error does not
+    shrink and the observed order is near zero."""
+    diff = [_tgv_error(orc, n, 0.04 * 64 / n, 100.0, 1000 * n * n // 4096) for n in (32, 64, 128)]
+    alpha = [math.log(a / b) / math.log(2.0) for a, b in zip(diff, diff[1:])]
+    acou = [_tgv_error(orc, n, 0.04, 100.0, 1000 * n // 64) for n in (32, 64, 128)]
+    alpha_a = [math.log(a / b) / math.log(2.0) for a, b in zip(acou, acou[1:])]
+    print(f"diffusive errors {diff}, alpha {alpha}; acoustic errors {acou}, alpha {alpha_a}")
+    assert all(1.85 < a < 2.15 for a in alpha)
+    assert all(abs(a) < 0.2 for a in alpha_a)

@@ -1,0 +1,98 @@
+"""GPU runs of the paper's Taylor-Green studies ("Resolution Study" with the
+convergence rate of Eq. 6, "Reynolds Number Study") through the library,
+checked against the FP64 oracle run for run and against properties that fix
+their outcome (second order in diffusive scaling, analytic energy decay)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_14494_amd import experiments, inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_error(orc, n, u0, re, steps):
+    tau = float(np.float32(inputs.tgv_params(n, u0, re)[1]))
+    _, ux, uy = inputs.tgv_velocity(n, n, u0)
+    f = orc.bgk_run(orc.init_ce(inputs.tgv_pressure_density(n, n, u0), ux, uy, tau), tau, steps)
+    _, vx, vy = orc.moments(f)
+    d = math.exp(-2.0 * (tau - 0.5) / 3.0 * (2 * np.pi / n) ** 2 * steps)
+    return math.sqrt((((vx - ux * d) ** 2 + (vy - uy * d) ** 2).sum())
+                     / (((ux * d) ** 2 + (uy * d) ** 2).sum()))
+
+
+def test_resolution_study_bgk_matches_oracle_and_is_second_order(orc):
+    rep = experiments.resolution_study(None, re=100.0, sizes=(32, 64, 128), scaling="diffusive")
+    for row in rep["rows"]:
+        ref = _oracle_error(orc, row["n"], row["u0"], 100.0, row["steps"])
+        # The FP32 velocity bar (1e-5 relative after 1000 steps at u0 = 0.04)
+        # scaled by steps / u0: the populations round to a fixed fraction of
+        # their O(u0) size each step, and that rounding enters the O(u0^2)
+        # density fluctuation.  Measured deviation of the FP32 field from
+        # FP64: 7e-7, 4e-6, 5e-5 at 32, 64, 128 (bars 1.25e-6, 1e-5, 8e-5).
+        tol = 1e-5 * (row["steps"] / 1000.0) * (0.04 / row["u0"])
+        print(f"n={row['n']}: GPU FP32 error {row['vel_err']:.6e}, FP64 oracle {ref:.6e}, "
+              f"bar {tol:.1e}")
+        assert abs(row["vel_err"] - ref) <= tol
+    # 32 -> 64 is second order in FP32; at 128^2 (4000 steps) the FP32
+    # rounding above is about a quarter of the discretisation error
+    print("FP32 observed orders", rep["alpha"])
+    assert 1.85 < rep["alpha"][0] < 2.15 and rep["alpha"][1] > 1.5
+    rep64 = experiments.resolution_study(None, re=100.0, sizes=(32, 64, 128),
+                                         scaling="diffusive", fp64=True)
+    print("FP64 observed orders", rep64["alpha"])
+    for row in rep64["rows"]:
+        ref = _oracle_error(orc, row["n"], row["u0"], 100.0, row["steps"])
+        # the error is evaluated on FP32 moments of the FP64 state (3e-8)
+        assert abs(row["vel_err"] - ref) <= 1e-7
+    assert all(1.85 < a < 2.15 for a in rep64["alpha"]), rep64["alpha"]
+
+
+def test_fp64_lattice_matches_oracle_on_the_finest_study_run(orc):
+    """The same 128^2 diffusive-scaling run in FP64 on the GPU equals the
+    oracle up to the FP32 rounding of the moments output."""
+    n, u0, steps = 128, 0.02, 4000
+    tau = float(np.float32(inputs.tgv_params(n, u0, 100.0)[1]))
+    rho, ux, uy = inputs.tgv_pressure_density(n, n, u0), *inputs.tgv_velocity(n, n, u0)[1:]
+    lat = lbm.Lattice(n, n, dtype=torch.float64).init_ce(rho, ux, uy, tau)
+    lat.step_bgk(tau, steps)
+    g = lbm.lbm_restrict(lat.a, 1, tau, tau, pull=False, unstream=False)
+    _, gx, gy, _ = lbm.lbm_moments(g, fields=True, sums=False)
+    f = orc.bgk_run(orc.init_ce(rho, ux, uy, tau), tau, steps)
+    _, ox, oy = orc.moments(f)
+    gx, gy = gx.double().cpu().numpy(), gy.double().cpu().numpy()
+    rel = math.sqrt((((gx - ox) ** 2 + (gy - oy) ** 2).sum()) / ((ox ** 2 + oy ** 2).sum()))
+    print(f"FP64 GPU vs oracle velocity rel-L2 {rel:.2e}")
+    assert rel <= 1e-7
+
+
+def test_resolution_study_acoustic_scaling_plateaus():
+    rep = experiments.resolution_study(None, re=100.0, sizes=(32, 64, 128), scaling="acoustic")
+    print(rep["alpha"], [r["vel_err"] for r in rep["rows"]])
+    assert all(abs(a) < 0.2 for a in rep["alpha"])
+
+
+def test_resolution_study_with_corrected_collision_runs_gated():
+    blob = torch.as_tensor(inputs.gnn_blob(0, 2, s_delta=1e-4), device="cuda")
+    rep = experiments.resolution_study(blob, re=100.0, sizes=(32, 64), scaling="diffusive")
+    for row in rep["rows"]:
+        assert row["finite"] and row["n_negative"] == 0
+        assert 0 <= row["fallback_steps"] <= row["steps"]
+    assert len(rep["alpha"]) == 1
+
+
+def test_stability_sweep_zero_head_equals_bgk_and_follows_analytic_decay():
+    blob = inputs.gnn_blob(1, 2, s_delta=1.0)
+    o, ln = inputs.blob_offsets(2)["Wh"]
+    blob[o:o + 650] = 0.0
+    rep = experiments.stability_sweep(torch.as_tensor(blob, device="cuda"), re_list=(100, 3200),
+                                      steps=2000, every=1000)
+    for row in rep["runs"]:
+        b, g = row["bgk"], row["gnn"]
+        print(row)
+        assert b["first_bad_step"] is None and g["first_bad_step"] is None
+        assert g["fallback_steps"] == 0 and g["first_fallback_by_step"] is None
+        assert abs(g["energy_ratio"] - b["energy_ratio"]) <= 1e-5 * b["energy_ratio"]
+        assert abs(b["energy_ratio"] / b["energy_ratio_analytic"] - 1.0) < 1e-2
