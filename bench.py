@@ -270,7 +270,7 @@ def cpu_leg():
     import oracle
     from paper_2504_14494_amd import inputs
     oracle.build(force=False)
-    n, steps = 2048, 30
+    n, steps = 2048, 60
     rho, ux, uy = inputs.tgv_velocity(n, n, 0.04)
     f = oracle.init_equilibrium(rho, ux, uy)
     _, tau = inputs.tgv_params(n, 0.04, 1000.0)
