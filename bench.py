@@ -38,6 +38,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bgk_pull_8192_traffic.json")
 
 CSRC = os.path.join(ROOT, "paper_2504_14494_amd", "csrc")
 GNN_PMC_FILE = os.path.join(ROOT, "profiles", "gnn_step_2048_counters.json")
+SIMPLE_PMC_FILE = os.path.join(ROOT, "profiles", "simple_step_8192_counters.json")
+# Fig. 2 per-node network, minimum MFMA work per node: 12->64, 64->64, 64->10
+SIMPLE_MAC_PER_NODE = 12 * 64 + 64 * 64 + 64 * 10
 
 
 def _read(name):
@@ -52,6 +55,12 @@ def bgk_src_hash():
     a = body.index(b"constexpr int kBgkThreads")
     b = body.index(b"// ------", a)
     return hashlib.sha256(_read("lbm_common.hpp") + body[a:b]).hexdigest()[:16]
+
+
+def simple_src_hash():
+    """Hash of the sources of the fused per-node (Fig. 2) step."""
+    return hashlib.sha256(_read("gnn_common.hpp") + _read("gnn_layout.hpp") +
+                          _read("simple_kernels.hip") + _read("lbm_common.hpp")).hexdigest()[:16]
 
 
 def gnn_src_hash():
@@ -259,10 +268,23 @@ def simple_leg(n, steps, warmup, ms_bgk):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    return {"n": n, "ms_per_step": ms, "mlups": n * n / (ms * 1e-3) / 1e6, "steps": steps,
+    sec = ms * 1e-3
+    gbs = BGK_BYTES_PER_LU * n * n / sec / 1e9
+    mfma_tf = 2.0 * SIMPLE_MAC_PER_NODE * n * n / sec / 1e12
+    t = _committed(SIMPLE_PMC_FILE, simple_src_hash())
+    return {"n": n, "ms_per_step": ms, "mlups": n * n / sec / 1e6, "steps": steps,
             "fallback_steps": int(lat.n_fallback.item()),
-            "overhead_vs_bgk": round(ms / ms_bgk - 1.0, 4),
-            "network": "per-node 12->64->64 ReLU, 64->10 head, no message passing"}
+            "step_over_bgk_step": round(ms / ms_bgk, 3),
+            "network": "per-node 12->64->64 ReLU, 64->10 head, no message passing",
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": None if t is None else t.get("bytes_per_launch")},
+            "roofline_mfma": {"bound": "mfma", "achieved": round(mfma_tf, 1),
+                              "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(mfma_tf / MFMA_BF16_PEAK_TFLOPS, 4)},
+            "counters": None if t is None else {
+                k: t[k] for k in ("mfma_util", "valu_busy_tool", "valu_issue_est",
+                                  "traffic_over_algorithmic")}}
 
 
 def cpu_leg():

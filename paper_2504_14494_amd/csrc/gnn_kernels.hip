@@ -404,16 +404,35 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
       }
       f32x4 agg[4] = {};
       const uint32_t q0 = q == 0 ? 0xffffffffu : 0u;
-#pragma unroll
-      for (int d = 1; d < 9; ++d) {
-        u32x4 hj[2] = {frag_at(cx(d), cy(d), 0), frag_at(cx(d), cy(d), 1)};
+      // Pre-activation of the message from direction d (MFMA only).
+      auto message = [&](int d, f32x4(&acc)[4]) {
+        const u32x4 hj[2] = {frag_at(cx(d), cy(d), 0), frag_at(cx(d), cy(d), 1)};
         const u32x4 ed = {q0 & (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)), 0u, 0u, 0u};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          f32x4 acc = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
-          acc = mfma(wb[t][0], hj[0], acc);
-          acc = mfma(wb[t][1], hj[1], acc);
-          agg[t] += gelu4(acc);
+          acc[t] = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
+          acc[t] = mfma(wb[t][0], hj[0], acc[t]);
+          acc[t] = mfma(wb[t][1], hj[1], acc[t]);
+        }
+      };
+      // Software pipeline over the 8 edges: the MFMA chains of edge d + 1 are
+      // issued before the GELUs of edge d, so the matrix cores work while the
+      // VALU evaluates the previous messages.  Summation order is unchanged.
+      f32x4 acc[2][4];
+      message(1, acc[0]);
+#pragma unroll
+      for (int d = 1; d < 9; ++d) {
+        if (d < 8) message(d + 1, acc[d & 1]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) agg[t] += gelu4(acc[(d - 1) & 1][t]);
+        if (d < 8) {
+          // issue order: the two LDS reads of edge d + 1, then each of its 12
+          // MFMAs followed by 8 of the VALU instructions of edge d's GELUs
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+          }
         }
       }
       u32x4 ab[2] = {frag_from_acc(agg[0], agg[1]), frag_from_acc(agg[2], agg[3])};

@@ -29,31 +29,34 @@ using lbm::cy;
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-template <bool PULL>
-__device__ __forceinline__ void pops(const float *__restrict__ lat, int nx, int ny, int x, int y,
-                                     float (&g)[9]) {
-  if constexpr (PULL) {
-    lbm::pull9(lat, nx, ny, x, y, g);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = lat[lbm::pidx(nx, y, i, x)];
-  }
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of eight accumulators, rounded to a BF16 B-operand fragment.  Rounding
+// keeps the sign, so ReLU after rounding equals rounding after ReLU; on the
+// packed BF16 bits ReLU is a signed 16-bit max with zero (negative values,
+// -0 included, have the sign bit set), two values per instruction.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+  s16x2 h = __builtin_bit_cast(s16x2, v);
+  h = __builtin_elementwise_max(h, s16x2{0, 0});
+  return __builtin_bit_cast(uint32_t, h);
 }
 
-__device__ __forceinline__ f32x4 relu4(f32x4 v) {
-  return f32x4{v.x > 0.0f ? v.x : 0.0f, v.y > 0.0f ? v.y : 0.0f, v.z > 0.0f ? v.z : 0.0f,
-               v.w > 0.0f ? v.w : 0.0f};
+__device__ __forceinline__ u32x4 relu_frag(f32x4 lo, f32x4 hi) {
+  u32x4 r = frag_from_acc(lo, hi);
+  return u32x4{relu_bf16x2(r.x), relu_bf16x2(r.y), relu_bf16x2(r.z), relu_bf16x2(r.w)};
 }
 
-// Eq. 3 with the projected correction at one node (same arithmetic as the
-// message-passing head).
+// Eq. 3 with the projected correction at one node.  The sigmoid and the
+// relaxation rate use the hardware exp2 and reciprocal (about 1 ulp each);
+// z0 = 0 still gives tau_adj = 1 exactly (2^0 = 1, 1/2 = 0.5).
 __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], float tau,
                                         float sdelta) {
   float drho, rho, u, v, uu;
   lbm::node_moments(g, drho, rho, u, v, uu);
-  float sig = 1.0f / (1.0f + expf(-z[0]));
+  constexpr float kLog2e = 1.4426950408889634f;
+  float sig = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z[0] * kLog2e));
   float tau_adj = 0.5f + sig;
-  float omega = 1.0f / (tau * tau_adj);
+  float omega = __builtin_amdgcn_rcpf(tau * tau_adj);
   float m0 = 0.0f, mx = 0.0f, my = 0.0f;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -75,25 +78,25 @@ __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], f
 // A wave takes 64 consecutive nodes of one lattice row, grid-stride, one
 // node per lane for everything that is per node: the coalesced pull of the
 // nine populations (kept in registers for the collision), the moments and the
-// 12 normalised features (rounded to BF16 into a wave-private LDS slot), and
-// the collision.  The network runs in between on MFMA, four column blocks of
-// 16 nodes with lane (n, q) = (node, channel group); the head outputs go back
-// to one node per lane through LDS.  Weights sit in LDS so that the kernel
-// keeps enough waves in flight to hide the loads.
-constexpr int kZStride = NOUT + 1;   // odd stride: the 64 lanes' z rows spread over banks
+// 12 normalised features (rounded to BF16 into the node's LDS slot), and the
+// collision.  The network runs in between on MFMA, four column blocks of 16
+// nodes with lane (n, q) = (node, channel group); each block reads its nodes'
+// features and then writes their head outputs into the same slots.  Weight
+// fragments and the (per channel group) bias fragments sit in LDS, which with
+// one 48-byte slot per node keeps the block at 27 KB and five blocks per CU.
+constexpr int kSlot = 12;   // dwords per node: 8 for the features, then 10 head outputs
+
+constexpr int kBlocksPerCu = 5;   // resident blocks (LDS 27 KB, <= 102 registers)
 
 template <bool PULL>
-__global__ __launch_bounds__(kThreads) void simple_step_kernel(
+__global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int batch, int nx, int ny,
     const float *__restrict__ tau_arr, float tau_s, const uint8_t *__restrict__ pack,
     FragLayout F, float *__restrict__ head_out, double *__restrict__ pmass,
     unsigned *__restrict__ pflag) {
-  __shared__ u32x4 w_s[14 * 64];               // W1 (4), W2 (8), Wh (2) fragments
-  __shared__ f32x4 b_s[9 * 64];                // b1 (4), b2 (4), bh (1)
-  __shared__ uint32_t feat_s[kWaves][64 * 8];  // 16 BF16 features per node (12 used)
-  __shared__ float zb[kWaves][64 * kZStride];
-  __shared__ double red_m[kThreads];
-  __shared__ unsigned red_f[kThreads];
+  __shared__ u32x4 w_s[14 * 64];   // W1 (4), W2 (8), Wh (2) fragments
+  __shared__ f32x4 b_s[9 * 4];     // b1 (4), b2 (4), bh (1), per channel group
+  __shared__ __attribute__((aligned(16))) uint32_t slot_s[kWaves][64 * kSlot];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
   {
@@ -104,10 +107,11 @@ __global__ __launch_bounds__(kThreads) void simple_step_kernel(
       int src_f = f < 4 ? F.W1 + f : (f < 12 ? F.W2 + (f - 4) : F.WH + (f - 12));
       w_s[k] = frags[(size_t)src_f * 64 + l];
     }
-    for (int k = threadIdx.x; k < 9 * 64; k += kThreads) {
-      int b = k >> 6, l = k & 63;
+    // a bias fragment holds rows 4q..4q+3 for every node column: lane 16 q
+    if (threadIdx.x < 9 * 4) {
+      int b = threadIdx.x >> 2, g = threadIdx.x & 3;
       int src_b = b < 4 ? F.B1 + b : (b < 8 ? F.B2 + (b - 4) : F.BH);
-      b_s[k] = bias[(size_t)src_b * 64 + l];
+      b_s[threadIdx.x] = bias[(size_t)src_b * 64 + 16 * g];
     }
   }
   const float *cst = (const float *)(pack + F.const_off);
@@ -119,24 +123,45 @@ __global__ __launch_bounds__(kThreads) void simple_step_kernel(
     isg[k] = 1.0f / cst[C_SIGMA + k];
   }
   __syncthreads();
-  uint32_t *fw = feat_s[wave];
-  float *z_w = zb[wave];
+  uint32_t *sw = slot_s[wave];
   double mass_acc = 0.0;
   unsigned flag_acc = 0;
 
-  const long long cxn = (nx + 63) / 64;
-  const long long nchunks = (long long)batch * ny * cxn;
-  for (long long c = (long long)blockIdx.x * kWaves + wave; c < nchunks;
-       c += (long long)gridDim.x * kWaves) {
-    const int xc = (int)(c % cxn);
-    const long long by = c / cxn;
-    const int y = (int)(by % ny), b = (int)(by / ny);
-    const size_t lat_off = (size_t)b * ny * 9 * nx;
-    const float *lat = src + lat_off;
+  // Chunks (b, y, xc) of 64 nodes, walked grid-stride.  The walk is
+  // wave-uniform (scalar registers): one division at the start, then a
+  // constant step with carries, so no per-lane index arithmetic is spent on it.
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int cxn = (nx + 63) >> 6;
+  const int nchunks = batch * ny * cxn;   // < 2^31: batch * nx * ny < 2^31
+  const int stride = gridDim.x * kWaves;
+  const int step_x = stride % cxn, step_y = stride / cxn;
+  int c = blockIdx.x * kWaves + wave_u;
+  int xc = c % cxn, y = (c / cxn) % ny, b = c / cxn / ny;
+  const size_t row = (size_t)9 * nx;
+  for (; c < nchunks; c += stride) {
+    const float *lat = src + (size_t)b * ny * row;
     const int x = xc * 64 + lane;
     const bool valid = x < nx;
     float gp[9];
-    pops<PULL>(lat, nx, ny, valid ? x : x % nx, y, gp);
+    {
+      // rows y - 1, y, y + 1 (uniform) and columns x - 1, x, x + 1 (per lane)
+      const int xv = valid ? x : nx - 1;
+      const float *r0 = lat + (size_t)(y == 0 ? ny - 1 : y - 1) * row;
+      const float *r1 = lat + (size_t)y * row;
+      const float *r2 = lat + (size_t)(y == ny - 1 ? 0 : y + 1) * row;
+      const int xs0 = xv == 0 ? nx - 1 : xv - 1, xs2 = xv == nx - 1 ? 0 : xv + 1;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if constexpr (PULL) {
+          // g_i(x, y) = post_i(x - c_ix, y - c_iy)
+          const float *r = cy(i) > 0 ? r0 : (cy(i) < 0 ? r2 : r1);
+          const int xsrc = cx(i) > 0 ? xs0 : (cx(i) < 0 ? xs2 : xv);
+          gp[i] = r[i * nx + xsrc];
+        } else {
+          gp[i] = r1[i * nx + xv];
+        }
+      }
+    }
     {
       float drho, rho, u, v, uu;
       lbm::node_moments(gp, drho, rho, u, v, uu);
@@ -145,55 +170,59 @@ __global__ __launch_bounds__(kThreads) void simple_step_kernel(
       float ft[NFEAT];
 #pragma unroll
       for (int k = 0; k < NFEAT; ++k) ft[k] = (raw[k] - mu[k]) * isg[k];
-      u32x4 *o = (u32x4 *)(fw + lane * 8);
+      u32x4 *o = (u32x4 *)(sw + lane * kSlot);
       o[0] = u32x4{pack_bf16(ft[0], ft[1]), pack_bf16(ft[2], ft[3]), pack_bf16(ft[4], ft[5]),
                    pack_bf16(ft[6], ft[7])};
       o[1] = u32x4{pack_bf16(ft[8], ft[9]), pack_bf16(ft[10], ft[11]), 0u, 0u};
     }
     wave_lds_sync();
-#pragma unroll 1
+#pragma unroll 4
     for (int grp = 0; grp < 4; ++grp) {
       int wo = lane;
       asm volatile("" : "+v"(wo));
       const u32x4 *w = w_s + wo;
-      const f32x4 *bs = b_s + wo;
-      const u32x4 xb = q < 2 ? *(const u32x4 *)(fw + (16 * grp + n) * 8 + 4 * q)
-                             : u32x4{0u, 0u, 0u, 0u};
+      const f32x4 *bs = b_s + q;
+      uint32_t *slot = sw + (16 * grp + n) * kSlot;
+      const u32x4 xb = q < 2 ? *(const u32x4 *)(slot + 4 * q) : u32x4{0u, 0u, 0u, 0u};
       f32x4 a[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) a[t] = relu4(mfma(w[t * 64], xb, bs[t * 64]));
-      const u32x4 e1[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
+      for (int t = 0; t < 4; ++t) a[t] = mfma(w[t * 64], xb, bs[t * 4]);
+      const u32x4 e1[2] = {relu_frag(a[0], a[1]), relu_frag(a[2], a[3])};
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        a[t] = relu4(mfma(w[(5 + 2 * t) * 64], e1[1],
-                          mfma(w[(4 + 2 * t) * 64], e1[0], bs[(4 + t) * 64])));
-      const u32x4 hb[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
-      const f32x4 z = mfma(w[13 * 64], hb[1], mfma(w[12 * 64], hb[0], bs[8 * 64]));
-      const float zz[4] = {z.x, z.y, z.z, z.w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int k = 4 * q + e;
-        if (k < NOUT) z_w[(16 * grp + n) * kZStride + k] = zz[e];
-      }
+        a[t] = mfma(w[(5 + 2 * t) * 64], e1[1], mfma(w[(4 + 2 * t) * 64], e1[0], bs[(4 + t) * 4]));
+      const u32x4 hb[2] = {relu_frag(a[0], a[1]), relu_frag(a[2], a[3])};
+      const f32x4 z = mfma(w[13 * 64], hb[1], mfma(w[12 * 64], hb[0], bs[8 * 4]));
+      // the features of these 16 nodes are consumed (z depends on them):
+      // their slots take the head outputs, rows 4q..4q+3
+      if (q < 2) *(f32x4 *)(slot + 4 * q) = z;
+      else if (q == 2) *(float2 *)(slot + 8) = float2{z.x, z.y};
     }
     wave_lds_sync();
     if (valid) {
       float z[NOUT];
+      {
+        const f32x4 *zs = (const f32x4 *)(sw + lane * kSlot);
+        const f32x4 z0 = zs[0], z1 = zs[1], z2 = zs[2];
+        const float zz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w, z2.x, z2.y, z2.z, z2.w};
 #pragma unroll
-      for (int k = 0; k < NOUT; ++k) z[k] = z_w[lane * kZStride + k];
-      const float tau = tau_arr ? tau_arr[b] : tau_s;
+        for (int k = 0; k < NOUT; ++k) z[k] = zz[k];
+      }
+      const float tau = tau_arr ? tau_arr[b] : tau_s;  // b < batch: c < nchunks
       collide(gp, z, tau, sdelta);
-      float *d = dst + lat_off + (size_t)y * 9 * nx + x;
-      double msum = 0.0;
+      float *d = dst + (size_t)b * ny * row + (size_t)y * row + x;
+      // node mass in FP32 (rounding ~1e-9 per node, ~1e-13 of the lattice
+      // mass), accumulated over the nodes in FP64
+      float msum = 0.0f;
       unsigned bad = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
+        __builtin_nontemporal_store(gp[i], d + i * nx);
         float f = gp[i] + lbm::wgt<float>(i);
         bad |= (f >= 0.0f && f < INFINITY) ? 0u : 1u;
-        msum += (double)gp[i];
+        msum += gp[i];
       }
-      mass_acc += msum;
+      mass_acc += (double)msum;
       flag_acc |= bad;
       if (head_out) {
         const size_t node = ((size_t)b * ny + y) * nx + x;
@@ -201,8 +230,22 @@ __global__ __launch_bounds__(kThreads) void simple_step_kernel(
       }
     }
     wave_lds_sync();
+    xc += step_x;
+    y += step_y;
+    if (xc >= cxn) {
+      xc -= cxn;
+      ++y;
+    }
+    while (y >= ny) {
+      y -= ny;
+      ++b;
+    }
   }
 
+  // every wave is done with its slots: the reduction reuses them
+  __syncthreads();
+  double *red_m = (double *)&slot_s[0][0];
+  unsigned *red_f = &slot_s[0][0] + 2 * kThreads;
   red_m[threadIdx.x] = mass_acc;
   red_f[threadIdx.x] = flag_acc;
   __syncthreads();
@@ -253,7 +296,8 @@ static int launch_simple(bool pull, const float *src, float *dst, int batch, int
   if (int rc = launch_prep(params, 0, pack, s)) return rc;
   const long long chunks = (long long)batch * ny * ((nx + 63) / 64);
   long long blocks = (chunks + simple::kWaves - 1) / simple::kWaves;
-  long long cap = (long long)simple_device_cus() * 8;
+  // exactly the resident blocks: the grid-stride loop then ends evenly
+  long long cap = (long long)simple_device_cus() * simple::kBlocksPerCu;
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   const int nb = (int)(blocks < cap ? blocks : cap);
   nparts = nb;
