@@ -14,7 +14,8 @@ rocprofv3 counters).  Beside it:
                measured against a restricted FP64 512^2 run, with the time each
                needs (measured and projected from the large-lattice MLUPS);
                and the paper's resolution study (observed order, Eq. 6) and
-               Reynolds-number sweep, trained network beside plain BGK;
+               Reynolds-number sweep, trained network beside plain BGK, and
+               its Poiseuille channel (Eq. 5) with plain BGK;
   cpu_baseline the FP64 CPU oracle timed on the host on a bounded sample.
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -243,7 +244,14 @@ def studies_leg(blob):
                   "gnn_fallback_steps": r["gnn"]["fallback_steps"],
                   "bgk_energy_err": float(f"{r['bgk']['energy_err']:.4g}"),
                   "gnn_energy_err": float(f"{r['gnn']['energy_err']:.4g}")} for r in sw["runs"]]
-    return {"resolution_re100": res, "stability_64": {"steps": 20000, "runs": stab}}
+    pois = experiments.poiseuille_study()
+    return {"resolution_re100": res, "stability_64": {"steps": 20000, "runs": stab},
+            "poiseuille_bgk": {"ny": pois["ny"], "u_max": pois["u_max"],
+                               "runs": [{"re": r["re"], "tau": round(r["tau"], 5),
+                                         "max_rel_err": float(f"{r['max_rel_err']:.4g}"),
+                                         "slip_closed_form": float(
+                                             f"{r['slip_rel_closed_form']:.4g}")}
+                                        for r in pois["rows"]]}}
 
 
 def simple_leg(n, steps, warmup, ms_bgk):

@@ -131,6 +131,32 @@ int lbm_restrict(const double *g_fine, int nxf, int nyf, int factor,
                  double tau_f, double tau_c, int pull, int unstream,
                  float *g_coarse, void *stream);
 
+/* One step of channel flow between two resting walls under a body force
+ * (validation section, "Poiseuille Flow", Eq. 5), fused pull + forced
+ * collision, same layout and shifted storage as lbm_step_bgk.  The paper
+ * names no wall or forcing scheme; these are the textbook ones:
+ *  - halfway bounce-back at y = -1/2 and y = ny - 1/2 (channel height ny):
+ *    g_i(x, y) = src_i(x - cx_i, y - cy_i) when that row lies in the
+ *    channel, else src_opp(i)(x, y); x is periodic;
+ *  - body force rho * gx along x with Guo's forcing: u = (sum e_i f_i) / rho
+ *    + gx / 2, f^eq at that u, plus (1 - 1/(2 tau)) w_i [3 (e_i - u)
+ *    + 9 (e_i . u) e_i] . F.
+ * tau must exceed 1/2.  The buffers must not overlap.  Steady state: the
+ * parabola gx / (2 nu) (y + 1/2)(ny - y - 1/2), nu = (tau - 1/2) / 3, plus the
+ * uniform bounce-back slip gx (16 (tau - 1/2)^2 - 3) / (24 nu). */
+int lbm_step_channel(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                     float gx, void *stream);
+int lbm_step_channel_f64(const double *g_src, double *g_dst, int nx, int ny,
+                         double tau, double gx, void *stream);
+
+/* x-averaged velocity profile of a channel state as lbm_step_channel leaves
+ * it (post-collision populations f*, whose momentum includes the step's
+ * force): prof[y] = mean over x of (sum_i e_ix f*_i) / rho - gx / 2, the
+ * fluid velocity (sum_i e_ix f_i + F/2) / rho of the step; accumulated in
+ * FP64 in a fixed order.  prof: device double[ny]. */
+int lbm_channel_profile(const float *g, int nx, int ny, float gx, double *prof,
+                        void *stream);
+
 /* Plain copy of n floats (bandwidth reference for the BGK kernel). */
 int lbm_copy(const float *src, float *dst, size_t n, void *stream);
 

@@ -58,6 +58,9 @@ def lib():
         L.orc_unstream.argtypes = [pd, pd, i, i]
         L.orc_bgk_step.argtypes = [pd, pd, i, i, d]
         L.orc_bgk_run.argtypes = [pd, i, i, d, i]
+        L.orc_collide_forced.argtypes = [pd, pd, i, i, d, d]
+        L.orc_stream_channel.argtypes = [pd, pd, i, i]
+        L.orc_channel_run.argtypes = [pd, i, i, d, d, i]
         L.orc_observables.argtypes = [pd, i, i, pd, pd]
         L.orc_restrict.argtypes = [pd, i, i, i, d, d, i, pd]
         L.orc_bf16_round.argtypes = [d]
@@ -174,6 +177,34 @@ def bgk_run(f, tau: float, steps: int) -> np.ndarray:
     f = _f64(f).copy()
     lib().orc_bgk_run(_p(f), f.shape[2], f.shape[1], tau, steps)
     return f
+
+
+def collide_forced(f, tau: float, gx: float) -> np.ndarray:
+    """BGK collision with Guo's body-force term, force rho * gx along x."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().orc_collide_forced(_p(f), _p(out), f.shape[2], f.shape[1], tau, gx)
+    return out
+
+
+def stream_channel(f) -> np.ndarray:
+    """Streaming with halfway bounce-back walls at y = -1/2, ny - 1/2."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().orc_stream_channel(_p(f), _p(out), f.shape[2], f.shape[1])
+    return out
+
+
+def channel_run(f, tau: float, gx: float, steps: int) -> np.ndarray:
+    f = _f64(f).copy()
+    lib().orc_channel_run(_p(f), f.shape[2], f.shape[1], tau, gx, steps)
+    return f
+
+
+def channel_velocity(f, gx: float):
+    """Velocity of a forced state: u = (sum e f + rho g / 2) / rho."""
+    rho, ux, uy = moments(f)
+    return ux + 0.5 * gx, uy
 
 
 def observables(f, tgv=None) -> np.ndarray:

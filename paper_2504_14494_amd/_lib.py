@@ -23,6 +23,7 @@ LBM_WS_SIMPLE = 6
 EXPORTS = [
     "lbm_last_error", "lbm_init", "lbm_init_f64", "lbm_step_bgk", "lbm_step_bgk_f64",
     "lbm_stream", "lbm_init_ce", "lbm_init_ce_f64",
+    "lbm_step_channel", "lbm_step_channel_f64", "lbm_channel_profile",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
     "lbm_step_gnn", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
     "lbm_step_simple", "simple_forward", "gnn_gelu_rate",
@@ -66,6 +67,9 @@ def load(path: str = LIB_PATH):
         "lbm_step_bgk": ([vp, vp, i, i, f, vp], i),
         "lbm_step_bgk_f64": ([vp, vp, i, i, d, vp], i),
         "lbm_stream": ([vp, vp, i, i, i, vp], i),
+        "lbm_step_channel": ([vp, vp, i, i, f, f, vp], i),
+        "lbm_step_channel_f64": ([vp, vp, i, i, d, d, vp], i),
+        "lbm_channel_profile": ([vp, i, i, f, vp, vp], i),
         "lbm_init_ce": ([vp, i, i, vp, vp, vp, f, vp], i),
         "lbm_init_ce_f64": ([vp, i, i, vp, vp, vp, d, vp], i),
         "lbm_moments": ([vp, i, i, vp, vp, vp, ctypes.POINTER(LbmTgv), vp, vp, sz, vp], i),

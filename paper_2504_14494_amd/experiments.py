@@ -298,3 +298,40 @@ def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
             row[name] = r
         out.append(row)
     return {"n": n, "u0": u0, "steps": steps, "check_every": every, "runs": out}
+
+
+def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
+                     diffusion_times=4.0, fp64=False):
+    """Channel flow between resting walls (validation section, "Poiseuille
+    Flow", Eq. 5) at several Reynolds numbers Re = u_max ny / nu: each run
+    starts at rest and is driven by g = 8 nu u_max / ny^2 for
+    `diffusion_times` ny^2 / nu steps (the slowest transient then decays as
+    exp(-pi^2 diffusion_times)).  Reports the largest velocity error of the
+    x-averaged profile relative to the largest analytic velocity, next to
+    the closed-form bounce-back slip of the method."""
+    rows = []
+    for re in re_list:
+        nu = u_max * ny / re
+        tau = float(np.float32(3.0 * nu + 0.5))
+        nu = (tau - 0.5) / 3.0
+        g = float(np.float32(8.0 * nu * u_max / ny ** 2))
+        steps = int(math.ceil(diffusion_times * ny * ny / nu))
+        lat = lbm.Lattice(nx, ny, dtype=torch.float64 if fp64 else torch.float32)
+        lat.a.zero_()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        lat.step_channel(tau, g, steps)
+        t1.record()
+        torch.cuda.synchronize()
+        g32 = lat.a if not fp64 else lbm.lbm_restrict(lat.a, 1, tau, tau, pull=False,
+                                                      unstream=False)
+        prof = lbm.lbm_channel_profile(g32, g).cpu().numpy()
+        y = np.arange(ny)
+        ua = g / (2.0 * nu) * (y + 0.5) * (ny - y - 0.5)
+        slip = g * (16.0 * (tau - 0.5) ** 2 - 3.0) / (24.0 * nu)
+        rows.append({"re": re, "tau": tau, "g": g, "steps": steps,
+                     "max_rel_err": float(np.abs(prof - ua).max() / ua.max()),
+                     "slip_rel_closed_form": float(slip / ua.max()),
+                     "seconds": t0.elapsed_time(t1) * 1e-3})
+    return {"ny": ny, "nx": nx, "u_max": u_max, "fp64": fp64, "rows": rows}

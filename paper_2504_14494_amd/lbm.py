@@ -17,6 +17,7 @@ from ._lib import LbmFallback, LbmTgv, check
 
 __all__ = [
     "lbm_init", "lbm_init_ce", "lbm_step_bgk", "lbm_stream", "lbm_moments", "lbm_restrict", "lbm_copy",
+    "lbm_step_channel", "lbm_channel_profile",
     "lbm_workspace_bytes", "Workspace", "Lattice",
 ]
 
@@ -107,6 +108,37 @@ def lbm_step_bgk(src: torch.Tensor, dst: torch.Tensor, tau: float):
         raise TypeError("populations must be float32 or float64")
     check(rc, "lbm_step_bgk")
     return dst
+
+
+def lbm_step_channel(src: torch.Tensor, dst: torch.Tensor, tau: float, gx: float):
+    """One step of the forced channel (walls at y = -1/2 and ny - 1/2,
+    periodic in x, body force rho * gx along x)."""
+    _need(src, src.dtype, "src")
+    _need(dst, src.dtype, "dst")
+    nx, ny = _pop_dims(src)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst shapes differ")
+    if src.dtype == torch.float32:
+        rc = _lib.load().lbm_step_channel(_ptr(src), _ptr(dst), nx, ny, float(tau), float(gx),
+                                          _stream())
+    elif src.dtype == torch.float64:
+        rc = _lib.load().lbm_step_channel_f64(_ptr(src), _ptr(dst), nx, ny, float(tau),
+                                              float(gx), _stream())
+    else:
+        raise TypeError("populations must be float32 or float64")
+    check(rc, "lbm_step_channel")
+    return dst
+
+
+def lbm_channel_profile(g: torch.Tensor, gx: float) -> torch.Tensor:
+    """x-averaged fluid velocity u_x(y) of a channel state as
+    lbm_step_channel leaves it (post-collision), FP64 [ny]."""
+    _need(g, torch.float32, "g")
+    nx, ny = _pop_dims(g)
+    prof = torch.empty(ny, dtype=torch.float64, device=g.device)
+    check(_lib.load().lbm_channel_profile(_ptr(g), nx, ny, float(gx), _ptr(prof), _stream()),
+          "lbm_channel_profile")
+    return prof
 
 
 def lbm_stream(src: torch.Tensor, dst: torch.Tensor = None):
@@ -204,6 +236,13 @@ class Lattice:
     def step_bgk(self, tau: float, n: int = 1):
         for _ in range(n):
             lbm_step_bgk(self.a, self.b, tau)
+            self.a, self.b = self.b, self.a
+            self.steps += 1
+        return self
+
+    def step_channel(self, tau: float, gx: float, n: int = 1):
+        for _ in range(n):
+            lbm_step_channel(self.a, self.b, tau, gx)
             self.a, self.b = self.b, self.a
             self.steps += 1
         return self
