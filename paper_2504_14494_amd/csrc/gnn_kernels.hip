@@ -371,11 +371,29 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
     const size_t lat_nodes = (size_t)b * ny * nx;
 
     __syncthreads();  // weights staged / previous tile no longer read
-    for (int k = threadIdx.x; k < HNODES * 8; k += kThreads) {
-      int ln = k >> 3, c = k & 7;
-      int gx = wrapi(x0 - 1 + ln % HALO, nx), gy = wrapi(y0 - 1 + ln / HALO, ny);
-      const u32x4 *srcp = (const u32x4 *)(hin + (lat_nodes + (size_t)gy * nx + gx) * HID);
-      *(u32x4 *)(hs + ln * kNodeBytes + c * 16) = srcp[c];
+    {
+      // chunk k = threadIdx.x + 256 j: node ln = k / 8 of the halo, 16-byte
+      // chunk c = k % 8.  ln advances by 32 = 18 + 14 per j, so the halo
+      // coordinates step without a division, and the periodic wrap of a
+      // coordinate that is at most one period off is a compare.
+      const int c = threadIdx.x & 7;
+      int ln = threadIdx.x >> 3;
+      int hy = ln / HALO, hx = ln - hy * HALO;
+      for (; ln < HNODES; ln += kThreads / 8) {
+        int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        if (gx >= nx) gx = wrapi(gx, nx);  // lattices narrower than the halo
+        if (gy >= ny) gy = wrapi(gy, ny);
+        const u32x4 *srcp = (const u32x4 *)(hin + (lat_nodes + (size_t)gy * nx + gx) * HID);
+        *(u32x4 *)(hs + ln * kNodeBytes + c * 16) = srcp[c];
+        hx += (kThreads / 8) % HALO;
+        hy += (kThreads / 8) / HALO;
+        if (hx >= HALO) {
+          hx -= HALO;
+          ++hy;
+        }
+      }
     }
     __syncthreads();
 
