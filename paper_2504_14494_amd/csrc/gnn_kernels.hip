@@ -169,14 +169,20 @@ __device__ __forceinline__ void node_pops(const float *__restrict__ lat, int nx,
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-// One wave per group of 16 consecutive nodes of a lattice row; groups are
-// taken grid-stride.  Lanes with x >= nx (ragged row end) compute on a
-// wrapped node and store nothing.
+// One wave per chunk of 64 consecutive nodes of a lattice row, chunks taken
+// grid-stride with a wave-uniform walk.  Per node (one lane each): the
+// coalesced pull of the nine populations, the moments and the 12 normalised
+// features, rounded to BF16 into the node's LDS slot (16 BF16, the last four
+// zero).  The two layers then run on MFMA over four column blocks of 16 nodes,
+// lane (n, q) = (node, channel group), reading the B operand from the slots:
+// group q < 2 takes features 8q..8q+7.  Lanes past the row end (ragged nx)
+// load a valid node and store nothing.
 template <bool PULL, bool SAVE>
 __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
     const float *__restrict__ g, int batch, int nx, int ny, const uint8_t *__restrict__ pack,
     FragLayout F, uint16_t *__restrict__ h0, uint16_t *__restrict__ save_x,
     uint16_t *__restrict__ save_e1) {
+  __shared__ __attribute__((aligned(16))) uint32_t slot_s[kWaves][64 * 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
   const u32x4 *frags = (const u32x4 *)(pack + F.frag_off);
@@ -192,63 +198,78 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
     b1[t] = load_bias(bias, F.B1 + t, lane);
     b2[t] = load_bias(bias, F.B2 + t, lane);
   }
-  // Normalisation constants of the 8 features this lane feeds (k = 8q + j).
-  float mu[8], isg[8];
+  float mu[NFEAT], isg[NFEAT];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    int k = 8 * q + j;
-    mu[j] = k < NFEAT ? cst[C_MU + k] : 0.0f;
-    isg[j] = k < NFEAT ? 1.0f / cst[C_SIGMA + k] : 0.0f;
+  for (int k = 0; k < NFEAT; ++k) {
+    mu[k] = cst[C_MU + k];
+    isg[k] = 1.0f / cst[C_SIGMA + k];
   }
-  const long long gxn = (nx + 15) / 16;
-  const long long ngroups = (long long)batch * ny * gxn;
-  for (long long grp = (long long)blockIdx.x * kWaves + wave; grp < ngroups;
-       grp += (long long)gridDim.x * kWaves) {
-    int xg = (int)(grp % gxn);
-    long long by = grp / gxn;
-    int y = (int)(by % ny), b = (int)(by / ny);
-    int x = xg * 16 + n;
-    bool valid = x < nx;
-    int xc = valid ? x : x % nx;
-    float feat[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) feat[j] = 0.0f;
-    if (q < 2) {
+  uint32_t *sw = slot_s[__builtin_amdgcn_readfirstlane(wave)];
+
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int cxn = (nx + 63) >> 6;
+  const int nchunks = batch * ny * cxn;   // < 2^31: batch * nx * ny < 2^31
+  const int stride = gridDim.x * kWaves;
+  const int step_x = stride % cxn, step_y = stride / cxn;
+  int c = blockIdx.x * kWaves + wave_u;
+  int xc = c % cxn, y = (c / cxn) % ny, b = c / cxn / ny;
+  for (; c < nchunks; c += stride) {
+    const float *lat = g + (size_t)b * ny * 9 * nx;
+    {
+      const int x = xc * 64 + lane;
       float gp[9];
-      node_pops<PULL>(g + (size_t)b * ny * 9 * nx, nx, ny, xc, y, gp);
+      node_pops<PULL>(lat, nx, ny, x < nx ? x : nx - 1, y, gp);
       float drho, rho, u, v, uu;
       lbm::node_moments(gp, drho, rho, u, v, uu);
-      const float all[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
+      const float raw[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
                                 gp[6], gp[7], gp[8], drho, u,     v};
+      float ft[NFEAT];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        float raw = q == 0 ? all[j] : (j < NFEAT - 8 ? all[8 + (j < NFEAT - 8 ? j : 0)] : 0.0f);
-        feat[j] = (q == 0 || j < NFEAT - 8) ? (raw - mu[j]) * isg[j] : 0.0f;
+      for (int k = 0; k < NFEAT; ++k) ft[k] = (raw[k] - mu[k]) * isg[k];
+      u32x4 *o = (u32x4 *)(sw + lane * 8);
+      o[0] = u32x4{pack_bf16(ft[0], ft[1]), pack_bf16(ft[2], ft[3]), pack_bf16(ft[4], ft[5]),
+                   pack_bf16(ft[6], ft[7])};
+      o[1] = u32x4{pack_bf16(ft[8], ft[9]), pack_bf16(ft[10], ft[11]), 0u, 0u};
+    }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int grp = 0; grp < 4; ++grp) {
+      const u32x4 xb = q < 2 ? *(const u32x4 *)(sw + (16 * grp + n) * 8 + 4 * q)
+                             : u32x4{0u, 0u, 0u, 0u};
+      f32x4 a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = gelu4(mfma(w1[t], xb, b1[t]));
+      u32x4 e1[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 acc = mfma(w2[t][0], e1[0], b2[t]);
+        a[t] = gelu4(mfma(w2[t][1], e1[1], acc));
+      }
+      u32x4 hb[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
+      const int x = xc * 64 + 16 * grp + n;
+      if (x < nx) {
+        size_t node = ((size_t)b * ny + y) * nx + x;
+        u32x4 *dst = (u32x4 *)(h0 + node * HID);
+        dst[q] = hb[0];
+        dst[4 + q] = hb[1];
+        if constexpr (SAVE) {
+          if (q < 2) ((u32x4 *)(save_x + node * 16))[q] = xb;
+          u32x4 *de = (u32x4 *)(save_e1 + node * HID);
+          de[q] = e1[0];
+          de[4 + q] = e1[1];
+        }
       }
     }
-    u32x4 xb = {pack_bf16(feat[0], feat[1]), pack_bf16(feat[2], feat[3]),
-                pack_bf16(feat[4], feat[5]), pack_bf16(feat[6], feat[7])};
-    f32x4 a[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] = gelu4(mfma(w1[t], xb, b1[t]));
-    u32x4 e1[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = mfma(w2[t][0], e1[0], b2[t]);
-      a[t] = gelu4(mfma(w2[t][1], e1[1], acc));
+    wave_lds_sync();
+    xc += step_x;
+    y += step_y;
+    if (xc >= cxn) {
+      xc -= cxn;
+      ++y;
     }
-    u32x4 hb[2] = {frag_from_acc(a[0], a[1]), frag_from_acc(a[2], a[3])};
-    if (valid) {
-      size_t node = ((size_t)b * ny + y) * nx + x;
-      u32x4 *dst = (u32x4 *)(h0 + node * HID);
-      dst[q] = hb[0];
-      dst[4 + q] = hb[1];
-      if constexpr (SAVE) {
-        if (q < 2) ((u32x4 *)(save_x + node * 16))[q] = xb;
-        u32x4 *de = (u32x4 *)(save_e1 + node * HID);
-        de[q] = e1[0];
-        de[4 + q] = e1[1];
-      }
+    while (y >= ny) {
+      y -= ny;
+      ++b;
     }
   }
 }
@@ -702,8 +723,8 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
     return (uint16_t *)at(ws, (r & 1) ? W.hB : W.hA);
   };
 
-  long long groups = (long long)batch * ny * ((nx + 15) / 16);
-  long long eblocks = (groups + kWaves - 1) / kWaves;
+  long long chunks = (long long)batch * ny * ((nx + 63) / 64);
+  long long eblocks = (chunks + kWaves - 1) / kWaves;
   int eb = (int)(eblocks < (long long)cus * 8 ? eblocks : (long long)cus * 8);
   uint16_t *sx = save ? (uint16_t *)at(saved, S.x) : nullptr;
   uint16_t *se = save ? (uint16_t *)at(saved, S.e1) : nullptr;
