@@ -11,8 +11,10 @@
 // Sizes follow the corrected collision's encoder and head: 12 -> 64 -> 64
 // (ReLU) -> 10.  The parameter blob is the zero-round layout:
 //   W1[64][12] b1[64] W2[64][64] b2[64] Wh[10][64] bh[10] | mu[12] sigma[12] s_delta
-// Weight fragments and the collision epilogue are shared with the
-// message-passing kernels (gnn_common.hpp, gnn_collide).
+// The weight fragments (gnn_prep_kernel) and the fallback gate kernels are
+// shared with the message-passing step; the collision epilogue is this
+// file's own, with the same arithmetic except the hardware exp2 and
+// reciprocal in the sigmoid and the relaxation rate.
 #include "gnn_common.hpp"
 #include "lbm_common.hpp"
 
