@@ -47,7 +47,7 @@ def fine_reference(u0, re, phase, n_fine, coarse_sizes, times_fine):
     out = {n: {} for n in coarse_sizes}
     done = 0
     for t in sorted(times_fine):
-        lat.step_bgk(tau_f, t - done)
+        lat.step_bgk(tau_f, t - done, graph=True)
         done = t
         for n in coarse_sizes:
             c = n_fine // n
@@ -73,9 +73,9 @@ def coarse_run(n, u0, re, phase, steps_list, blob=None, rounds=2):
     for s in sorted(steps_list):
         t0.record()
         if blob is None:
-            lat.step_bgk(tau, s - done)
+            lat.step_bgk(tau, s - done, graph=True)
         else:
-            lat.step_gnn(tau, s - done)
+            lat.step_gnn(tau, s - done, graph=True)
         t1.record()
         torch.cuda.synchronize()
         ms += t0.elapsed_time(t1)
@@ -213,10 +213,11 @@ def _fp32_view(lat, tau):
 
 
 def _advance(lat, blob, tau32, k):
+    # small lattices: whole chunks of steps replayed from captured HIP graphs
     if blob is None:
-        lat.step_bgk(tau32, k)
+        lat.step_bgk(tau32, k, graph=True)
     else:
-        lat.step_gnn(tau32, k)
+        lat.step_gnn(tau32, k, graph=True)
 
 
 def resolution_study(blob=None, rounds=2, re=100.0, sizes=(32, 64, 128), scaling="diffusive",
@@ -321,7 +322,7 @@ def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
-        lat.step_channel(tau, g, steps)
+        lat.step_channel(tau, g, steps, graph=True)
         t1.record()
         torch.cuda.synchronize()
         g32 = lat.a if not fp64 else lbm.lbm_restrict(lat.a, 1, tau, tau, pull=False,

@@ -195,24 +195,34 @@ class GnnLattice(Lattice):
         _, _, _, sums = lbm_moments(self.a, ws=self.ws)
         self.fallback.mass.copy_(sums[0:1])
 
-    def step_bgk(self, tau: float, n: int = 1):
-        super().step_bgk(tau, n)
+    def step_bgk(self, tau: float, n: int = 1, graph: bool = False):
+        super().step_bgk(tau, n, graph)
         if n:
             self.sync_mass()
         return self
 
-    def step_gnn(self, tau: float, n: int = 1, gate: bool = True):
+    def step_gnn(self, tau: float, n: int = 1, gate: bool = True, graph: bool = False):
         """Corrected steps: message passing for rounds >= 1, the fused
-        per-node network of Fig. 2 for rounds == 0."""
-        fb = self.fallback if gate else None
-        for _ in range(n):
+        per-node network of Fig. 2 for rounds == 0.  With the gate, the
+        fallback state is updated on the device every step, also inside a
+        captured graph."""
+        def step(src, dst, fb):
             if self.rounds == 0:
-                lbm_step_simple(self.a, self.b, tau, self.blob, fb, self.ws)
+                lbm_step_simple(src, dst, tau, self.blob, fb, self.ws)
             else:
-                lbm_step_gnn(self.a, self.b, tau, self.blob, self.rounds, fb, self.ws)
-            self.a, self.b = self.b, self.a
-            self.steps += 1
-        return self
+                lbm_step_gnn(src, dst, tau, self.blob, self.rounds, fb, self.ws)
+
+        fb = self.fallback if gate else None
+
+        def warm():
+            # same code path on copies: the gate state of the lattice is untouched
+            tmp = None
+            if gate:
+                tmp = Fallback(0.0, self.fallback.threshold)
+                tmp.mass.copy_(self.fallback.mass)
+            step(self.a.clone(), torch.empty_like(self.a), tmp)
+        return self._run(("gnn", float(tau), bool(gate)), lambda s, d: step(s, d, fb), warm, n,
+                         graph)
 
 
 def backward_ws_bytes(batch: int, nx: int, ny: int, rounds: int = 2) -> int:

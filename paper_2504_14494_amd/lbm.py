@@ -202,13 +202,60 @@ def lbm_copy(src: torch.Tensor, dst: torch.Tensor):
 
 
 class Lattice:
-    """A/B population buffers of one periodic D2Q9 lattice on the GPU."""
+    """A/B population buffers of one periodic D2Q9 lattice on the GPU.
+
+    Stepping methods take `graph=True` to run whole chunks of steps as one
+    captured HIP graph (torch.cuda.CUDAGraph over the library's launches on
+    the current stream), which removes the per-launch host cost that
+    dominates small lattices.  The graph holds the buffer addresses, so one
+    is captured per (step kind, parameters, buffer holding the state) and
+    replayed; results are bitwise those of the eager steps."""
+
+    GRAPH_CHUNK = 64   # steps per captured graph (even: the state returns to `a`)
 
     def __init__(self, nx: int, ny: int, dtype=torch.float32, device="cuda"):
         self.nx, self.ny = nx, ny
         self.a = torch.empty((ny, 9, nx), dtype=dtype, device=device)
         self.b = torch.empty_like(self.a)
         self.steps = 0
+        self._graphs = {}
+
+    def _capture(self, one_step, warmup):
+        """HIP graph of GRAPH_CHUNK steps from self.a, ping-ponging with
+        self.b.  `warmup()` runs one step on scratch copies first, on the
+        side stream, so that library state and workspaces exist before the
+        capture and the lattice itself does not advance."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            warmup()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            src, dst = self.a, self.b
+            for _ in range(self.GRAPH_CHUNK):
+                one_step(src, dst)
+                src, dst = dst, src
+        return g
+
+    def _run(self, key, one_step, warmup, n: int, graph: bool):
+        """n steps: whole chunks from a captured graph when `graph`, the rest
+        eagerly (one_step(src, dst) advances src into dst)."""
+        if graph and n >= self.GRAPH_CHUNK:
+            k = (key, self.a.data_ptr())
+            if k not in self._graphs:
+                self._graphs[k] = self._capture(one_step, warmup)
+            g = self._graphs[k]
+            for _ in range(n // self.GRAPH_CHUNK):
+                g.replay()
+            self.steps += (n // self.GRAPH_CHUNK) * self.GRAPH_CHUNK
+            n %= self.GRAPH_CHUNK
+        for _ in range(n):
+            one_step(self.a, self.b)
+            self.a, self.b = self.b, self.a
+            self.steps += 1
+        return self
 
     @property
     def g(self) -> torch.Tensor:
@@ -233,19 +280,21 @@ class Lattice:
         self.a.copy_(torch.as_tensor(g, dtype=self.a.dtype))
         return self
 
-    def step_bgk(self, tau: float, n: int = 1):
-        for _ in range(n):
-            lbm_step_bgk(self.a, self.b, tau)
-            self.a, self.b = self.b, self.a
-            self.steps += 1
-        return self
+    def step_bgk(self, tau: float, n: int = 1, graph: bool = False):
+        def one(src, dst):
+            lbm_step_bgk(src, dst, tau)
 
-    def step_channel(self, tau: float, gx: float, n: int = 1):
-        for _ in range(n):
-            lbm_step_channel(self.a, self.b, tau, gx)
-            self.a, self.b = self.b, self.a
-            self.steps += 1
-        return self
+        def warm():
+            one(self.a.clone(), torch.empty_like(self.a))
+        return self._run(("bgk", float(tau)), one, warm, n, graph)
+
+    def step_channel(self, tau: float, gx: float, n: int = 1, graph: bool = False):
+        def one(src, dst):
+            lbm_step_channel(src, dst, tau, gx)
+
+        def warm():
+            one(self.a.clone(), torch.empty_like(self.a))
+        return self._run(("channel", float(tau), float(gx)), one, warm, n, graph)
 
     def moments(self, analytic=None, fields=False):
         return lbm_moments(self.a, analytic, fields)

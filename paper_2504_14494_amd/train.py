@@ -103,11 +103,11 @@ def run_pairs(u0: float, re: float, phase, cfg: DataConfig, device="cuda"):
     ins, outs, cins = [], [], []
     done = cdone = 0
     for m in cfg.snapshot_steps():
-        lat.step_bgk(tau_f, fac * m - 1 - done)             # P_f(4m - 1)
+        lat.step_bgk(tau_f, fac * m - 1 - done, graph=True)  # P_f(4m - 1)
         done = fac * m - 1
         ins.append(lbm.lbm_restrict(lat.a, fac, tau_f, tau_c, pull=True, unstream=False))
         if clat is not None:
-            clat.step_bgk(tc32, m - 1 - cdone)              # P_c(m - 1)
+            clat.step_bgk(tc32, m - 1 - cdone, graph=True)   # P_c(m - 1)
             cdone = m - 1
             cins.append(lbm.lbm_stream(clat.a))
         lat.step_bgk(tau_f, fac)                            # P_f(4m + 3)

@@ -1,0 +1,84 @@
+"""Stepping through captured HIP graphs: chunks of library launches
+captured once and replayed must give bitwise the eager results, replay after
+replay, with eager work and synchronisation in between, for every step kind
+(BGK, channel, message-passing and per-node corrected steps with the
+device-side fallback gate, including steps that fall back)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_14494_amd import gnn, inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+CH = lbm.Lattice.GRAPH_CHUNK
+
+
+def _tgv(n, u0=0.04):
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
+    return rho, ux, uy
+
+
+def _twins(make):
+    eager, graphed = make(), make()
+    assert torch.equal(eager.a, graphed.a)
+    return eager, graphed
+
+
+def _check_replays(eager, graphed, advance, rounds=3, extra=5):
+    for r in range(rounds):
+        advance(eager, CH + extra, False)
+        advance(graphed, CH + extra, True)
+        torch.cuda.synchronize()
+        assert torch.equal(eager.a, graphed.a), f"replay {r}"
+        assert eager.steps == graphed.steps
+        # eager work between replays
+        lbm.lbm_moments(graphed.a)
+        torch.cuda.synchronize()
+
+
+def test_bgk_graph_replays_equal_eager_steps():
+    e, g = _twins(lambda: lbm.Lattice(48, 48).init(*_tgv(48)))
+    _check_replays(e, g, lambda lat, n, gr: lat.step_bgk(0.61, n, graph=gr))
+
+
+def test_graph_after_an_odd_eager_step_uses_the_swapped_buffers():
+    e, g = _twins(lambda: lbm.Lattice(33, 17).init(*inputs.tgv_velocity(33, 17, 0.03,
+                                                                         dtype=np.float32)))
+    e.step_bgk(0.7, 1)
+    g.step_bgk(0.7, 1)
+    _check_replays(e, g, lambda lat, n, gr: lat.step_bgk(0.7, n, graph=gr), rounds=2, extra=0)
+
+
+def test_channel_graph_replays_equal_eager_steps():
+    def make():
+        lat = lbm.Lattice(5, 24)
+        lat.a.zero_()
+        return lat
+    e, g = _twins(make)
+    _check_replays(e, g, lambda lat, n, gr: lat.step_channel(0.8, 1e-5, n, graph=gr))
+
+
+@pytest.mark.parametrize("rounds", [2, 0])
+def test_corrected_step_graph_replays_equal_eager_steps(rounds):
+    blob = torch.as_tensor(inputs.gnn_blob(3, rounds, s_delta=1e-4), device="cuda")
+    e, g = _twins(lambda: gnn.GnnLattice(40, 36, blob, rounds).init(*inputs.tgv_velocity(
+        40, 36, 0.04, dtype=np.float32)))
+    _check_replays(e, g, lambda lat, n, gr: lat.step_gnn(0.62, n, graph=gr), rounds=2)
+    assert torch.equal(e.fallback.mass, g.fallback.mass)
+    assert torch.equal(e.n_fallback, g.n_fallback)
+
+
+@pytest.mark.parametrize("rounds", [2, 0])
+def test_fallback_inside_a_graph_matches_eager(rounds):
+    """A head that drives populations negative makes every step fall back to
+    BGK; the gate decides on the device, inside the graph as in eager mode."""
+    blob = inputs.gnn_blob(4, rounds, s_delta=1.0)
+    o, _ = inputs.blob_offsets(rounds)["bh"]
+    blob[o + 1:o + 3] = np.float32([50, -50])
+    blob = torch.as_tensor(blob, device="cuda")
+    e, g = _twins(lambda: gnn.GnnLattice(32, 32, blob, rounds).init(*_tgv(32)))
+    _check_replays(e, g, lambda lat, n, gr: lat.step_gnn(0.7, n, graph=gr), rounds=2, extra=3)
+    assert int(g.n_fallback.item()) == g.steps
+    assert torch.equal(e.fallback.flags, g.fallback.flags)
+    assert torch.equal(e.fallback.mass, g.fallback.mass)
