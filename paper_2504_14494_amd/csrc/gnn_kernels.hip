@@ -206,14 +206,8 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
   }
   uint32_t *sw = slot_s[__builtin_amdgcn_readfirstlane(wave)];
 
-  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  const int cxn = (nx + 63) >> 6;
-  const int nchunks = batch * ny * cxn;   // < 2^31: batch * nx * ny < 2^31
-  const int stride = gridDim.x * kWaves;
-  const int step_x = stride % cxn, step_y = stride / cxn;
-  int c = blockIdx.x * kWaves + wave_u;
-  int xc = c % cxn, y = (c / cxn) % ny, b = c / cxn / ny;
-  for (; c < nchunks; c += stride) {
+  for (ChunkWalk cw(batch, nx, ny, kWaves, wave); cw.more(); cw.next()) {
+    const int xc = cw.xc, y = cw.y, b = cw.b;
     const float *lat = g + (size_t)b * ny * 9 * nx;
     {
       const int x = xc * 64 + lane;
@@ -261,16 +255,6 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
       }
     }
     wave_lds_sync();
-    xc += step_x;
-    y += step_y;
-    if (xc >= cxn) {
-      xc -= cxn;
-      ++y;
-    }
-    while (y >= ny) {
-      y -= ny;
-      ++b;
-    }
   }
 }
 

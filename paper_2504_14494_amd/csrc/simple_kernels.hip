@@ -129,18 +129,9 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
   double mass_acc = 0.0;
   unsigned flag_acc = 0;
 
-  // Chunks (b, y, xc) of 64 nodes, walked grid-stride.  The walk is
-  // wave-uniform (scalar registers): one division at the start, then a
-  // constant step with carries, so no per-lane index arithmetic is spent on it.
-  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  const int cxn = (nx + 63) >> 6;
-  const int nchunks = batch * ny * cxn;   // < 2^31: batch * nx * ny < 2^31
-  const int stride = gridDim.x * kWaves;
-  const int step_x = stride % cxn, step_y = stride / cxn;
-  int c = blockIdx.x * kWaves + wave_u;
-  int xc = c % cxn, y = (c / cxn) % ny, b = c / cxn / ny;
   const size_t row = (size_t)9 * nx;
-  for (; c < nchunks; c += stride) {
+  for (ChunkWalk cw(batch, nx, ny, kWaves, wave); cw.more(); cw.next()) {
+    const int xc = cw.xc, y = cw.y, b = cw.b;
     const float *lat = src + (size_t)b * ny * row;
     const int x = xc * 64 + lane;
     const bool valid = x < nx;
@@ -210,7 +201,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
 #pragma unroll
         for (int k = 0; k < NOUT; ++k) z[k] = zz[k];
       }
-      const float tau = tau_arr ? tau_arr[b] : tau_s;  // b < batch: c < nchunks
+      const float tau = tau_arr ? tau_arr[b] : tau_s;  // b < batch while cw.more()
       collide(gp, z, tau, sdelta);
       float *d = dst + (size_t)b * ny * row + (size_t)y * row + x;
       // node mass in FP32 (rounding ~1e-9 per node, ~1e-13 of the lattice
@@ -232,16 +223,6 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
       }
     }
     wave_lds_sync();
-    xc += step_x;
-    y += step_y;
-    if (xc >= cxn) {
-      xc -= cxn;
-      ++y;
-    }
-    while (y >= ny) {
-      y -= ny;
-      ++b;
-    }
   }
 
   // every wave is done with its slots: the reduction reuses them

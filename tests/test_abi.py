@@ -54,3 +54,41 @@ def test_channel_step_rejects_bad_arguments_before_any_device_work():
     assert b"overlap" in L.lbm_last_error()
     assert L.lbm_step_channel_f64(pa, pb, 4, 4, 0.3, 0.0, None) == EINVAL
     assert L.lbm_channel_profile(pa, 4, 4, 0.0, None, None) == EINVAL
+
+
+EWORKSPACE = -2   # LBM_EWORKSPACE
+
+
+def test_every_entry_point_rejects_bad_arguments_before_device_work():
+    """The documented error codes, returned before anything touches a GPU
+    (host buffers stand in for device pointers and are never read)."""
+    L = _lib.load()
+    bufs = [ctypes.create_string_buffer(4096) for _ in range(6)]
+    p = [ctypes.addressof(b) for b in bufs]
+    a, b, c, d, e, f = p
+    cases = [
+        ("lbm_init", (None, 4, 4, b, c, d, None), EINVAL),
+        ("lbm_init_f64", (a, 0, 4, b, c, d, None), EINVAL),
+        ("lbm_init_ce", (a, 4, 4, b, c, d, 0.0, None), EINVAL),
+        ("lbm_step_bgk", (a, a, 4, 4, 0.8, None), EINVAL),
+        ("lbm_step_bgk", (a, b, 4, 4, 0.0, None), EINVAL),
+        ("lbm_step_bgk_f64", (a, b, 4, -1, 0.8, None), EINVAL),
+        ("lbm_stream", (a, b, 4, 4, 0, None), EINVAL),
+        ("lbm_moments", (a, 4, 4, None, None, None, None, b, c, 0, None), EWORKSPACE),
+        ("lbm_restrict", (a, 10, 8, 4, 0.8, 0.6, 1, 0, b, None), EINVAL),
+        ("lbm_copy", (a + 4, b, 16, None), EINVAL),
+        ("gnn_gelu_rate", (a, 0, 10, None), EINVAL),
+        ("lbm_step_gnn", (a, b, 4, 4, 0.7, c, 2, None, d, 16, None), EWORKSPACE),
+        ("lbm_step_gnn", (a, b, 4, 4, -1.0, c, 2, None, d, 1 << 30, None), EINVAL),
+        ("gnn_forward", (a, a, 1, 4, 4, b, c, 2, None, None, 0, d, 1 << 30, None), EINVAL),
+        ("gnn_backward", (a, b, c, 1, 4, 4, d, e, 0, f, a, 1 << 30, None), EINVAL),
+        ("gnn_mse", (a, b, 0, 4, 4, 1.0, c, d, e, 1 << 30, None), EINVAL),
+        ("gnn_adam", (a, b, c, d, 16, 1e-3, 0.9, 0.999, 1e-8, 0, None), EINVAL),
+        ("lbm_step_simple", (a, b, 4, 4, -1.0, c, None, d, 1 << 30, None), EINVAL),
+        ("simple_forward", (a, a, 1, 4, 4, b, c, None, d, 1 << 30, None), EINVAL),
+    ]
+    for name, args, code in cases:
+        rc = getattr(L, name)(*args)
+        assert rc == code, (name, rc, L.lbm_last_error())
+        # the thread-local message names the entry point that failed
+        assert L.lbm_last_error().decode().startswith(name.split("_f64")[0]), name
