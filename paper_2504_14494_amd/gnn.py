@@ -195,6 +195,11 @@ class GnnLattice(Lattice):
         _, _, _, sums = lbm_moments(self.a, ws=self.ws)
         self.fallback.mass.copy_(sums[0:1])
 
+    def _graph_buffers(self):
+        fb = self.fallback
+        return super()._graph_buffers() + [self.blob, self.ws.buf, fb.flags, fb.n_fallback,
+                                           fb.mass]
+
     def step_bgk(self, tau: float, n: int = 1, graph: bool = False):
         super().step_bgk(tau, n, graph)
         if n:

@@ -239,14 +239,21 @@ class Lattice:
                 src, dst = dst, src
         return g
 
+    def _graph_buffers(self):
+        """Device buffers a captured step reads or writes; the graph keeps
+        them alive, so a later reallocation elsewhere (a grown workspace)
+        cannot leave it pointing at freed memory."""
+        return [self.a, self.b]
+
     def _run(self, key, one_step, warmup, n: int, graph: bool):
         """n steps: whole chunks from a captured graph when `graph`, the rest
         eagerly (one_step(src, dst) advances src into dst)."""
         if graph and n >= self.GRAPH_CHUNK:
             k = (key, self.a.data_ptr())
             if k not in self._graphs:
-                self._graphs[k] = self._capture(one_step, warmup)
-            g = self._graphs[k]
+                g = self._capture(one_step, warmup)
+                self._graphs[k] = (g, list(self._graph_buffers()))
+            g = self._graphs[k][0]
             for _ in range(n // self.GRAPH_CHUNK):
                 g.replay()
             self.steps += (n // self.GRAPH_CHUNK) * self.GRAPH_CHUNK

@@ -82,3 +82,21 @@ def test_fallback_inside_a_graph_matches_eager(rounds):
     assert int(g.n_fallback.item()) == g.steps
     assert torch.equal(e.fallback.flags, g.fallback.flags)
     assert torch.equal(e.fallback.mass, g.fallback.mass)
+
+
+def test_graph_keeps_its_buffers_when_the_workspace_grows():
+    """A captured graph holds the workspace it was captured with; growing the
+    lattice's workspace afterwards (a new buffer) leaves replays valid."""
+    blob = torch.as_tensor(inputs.gnn_blob(5, 2, s_delta=1e-4), device="cuda")
+    e, g = _twins(lambda: gnn.GnnLattice(40, 36, blob, 2).init(*inputs.tgv_velocity(
+        40, 36, 0.04, dtype=np.float32)))
+    e.step_gnn(0.66, CH)
+    g.step_gnn(0.66, CH, graph=True)
+    old = g.ws.buf
+    g.ws.get(old.numel() * 2)
+    assert g.ws.buf.data_ptr() != old.data_ptr()
+    for _ in range(2):
+        e.step_gnn(0.66, CH + 3)
+        g.step_gnn(0.66, CH + 3, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(e.a, g.a)
