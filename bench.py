@@ -206,12 +206,24 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     BGK at 128^2 and 256^2, all against a restricted FP64 512^2 run."""
     from paper_2504_14494_amd import experiments, train
     t0 = time.perf_counter()
-    tr, rep = train.train(train.DataConfig(), steps=2000, batch=32)
+    data = train.datasets(train.DataConfig())
+    tr, rep = train.train(train.DataConfig(), steps=2000, batch=32, data=data)
     out = {"train_seconds": round(time.perf_counter() - t0, 1),
+           "train_data_seconds": round(rep["data_seconds"], 2),
+           "train_optimizer_seconds": round(rep["optimizer_seconds"], 2),
+           "train_samples_per_s": round(rep["samples_per_s"], 1),
            "heldout_loss_over_bgk": rep["heldout_rel_loss_after"]}
     out.update(experiments.fixed_error_report(tr.blob, mlups_bgk=mlups_bgk,
                                               mlups_gnn=mlups_gnn))
     out["studies"] = studies_leg(tr.blob)
+    # ablation of message passing: the paper's Fig. 2 per-node network
+    # trained the same way on the same pairs
+    tr0, rep0 = train.train(train.DataConfig(), steps=2000, batch=32, rounds=0, data=data)
+    f2 = experiments.fixed_error_report(tr0.blob, rounds=0)
+    out["fig2_network"] = {"heldout_loss_over_bgk": rep0["heldout_rel_loss_after"],
+                           "train_samples_per_s": round(rep0["samples_per_s"], 1),
+                           "errors_128": f2["errors"]["gnn_128"],
+                           "fallback_steps": f2["fallback_steps"]}
     return out
 
 

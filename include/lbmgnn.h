@@ -231,9 +231,11 @@ int gnn_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
                 void *workspace, size_t ws_bytes, void *stream);
 
 /* Gradient of a scalar loss with respect to the trainable parameters, given
- * dL_dgpost = dL/d g_post at the output of the gnn_forward call that filled
- * `saved` (same g_pre, tau and params).  BF16 rounding of the forward is
- * treated as the identity.  grad: device float[gnn_param_count(n_rounds)],
+ * dL_dgpost = dL/d g_post at the output of the forward call that filled
+ * `saved` (same g_pre, tau and params): gnn_forward for n_rounds >= 1 (GELU
+ * message-passing network), simple_forward for n_rounds = 0 (the per-node
+ * ReLU network of Fig. 2).  BF16 rounding of the forward is treated as the
+ * identity.  grad: device float[gnn_param_count(n_rounds)],
  * overwritten.  workspace: >= lbm_workspace_bytes(LBM_WS_GNN_BACKWARD, ...). */
 int gnn_backward(const float *dL_dgpost, const float *g_pre, const void *saved,
                  int batch, int nx, int ny, const float *tau,
@@ -252,9 +254,13 @@ int lbm_step_simple(const float *g_src, float *g_dst, int nx, int ny, float tau,
                     size_t ws_bytes, void *stream);
 /* The same collision alone (no streaming) on a batch of pre-collision states
  * [batch][ny][9][nx], tau: device float[batch]; head_out NULL or
- * [batch][ny][nx][10]. */
+ * [batch][ny][nx][10].  saved: NULL for inference, else a device buffer of
+ * >= lbm_workspace_bytes(LBM_WS_GNN_SAVED, batch, nx, ny, 0) bytes that
+ * receives what gnn_backward (n_rounds = 0) needs: the BF16 features, both
+ * hidden layers (fragment order) and the FP32 head outputs per node. */
 int simple_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
-                   const float *tau, const float *params, float *head_out, void *workspace,
+                   const float *tau, const float *params, float *head_out,
+                   void *saved, size_t saved_bytes, void *workspace,
                    size_t ws_bytes, void *stream);
 
 /* Eq. 4 with N = batch*nx*ny nodes: loss = scale/N * sum (a - b)^2 over all

@@ -84,7 +84,7 @@ def load(path: str = LIB_PATH):
         "gnn_mse": ([vp, vp, i, i, i, d, vp, vp, vp, sz, vp], i),
         "gnn_adam": ([vp, vp, vp, vp, sz, f, f, f, f, i, vp], i),
         "lbm_step_simple": ([vp, vp, i, i, f, vp, ctypes.POINTER(LbmFallback), vp, sz, vp], i),
-        "simple_forward": ([vp, vp, i, i, i, vp, vp, vp, vp, sz, vp], i),
+        "simple_forward": ([vp, vp, i, i, i, vp, vp, vp, vp, sz, vp, sz, vp], i),
         "lbm_workspace_bytes": ([i, i, i, i, i], sz),
     }
     for name, (args, res) in sig.items():

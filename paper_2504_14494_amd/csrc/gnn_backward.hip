@@ -1,7 +1,8 @@
 // Backward pass of the GNN-corrected collision and the pieces of one
 // training step (paper: Training Methodology, loss of Eq. 4): gradient of a
 // scalar loss with respect to every trainable parameter, the MSE loss and an
-// Adam update.
+// Adam update.  n_rounds >= 1 is the message-passing network (GELU);
+// n_rounds = 0 the per-node network of Fig. 2 (ReLU): head, then encoder.
 //
 // The forward saved, per node, the BF16 values the MFMAs consumed: features
 // x, first encoder layer e1, node states h_0..h_R and summed messages a_1..a_R,
@@ -548,6 +549,19 @@ __global__ __launch_bounds__(kBT) void bwd_edge_send_kernel(
 
 // ------------------------------------------------------------- encoder ---
 
+// Derivative of the activation at the recomputed pre-activation: GELU (tanh
+// form) for the message-passing network, ReLU (1 for p > 0, else 0) for the
+// per-node network of Fig. 2.
+template <int ACT>
+__device__ __forceinline__ f32x4 act_grad4(f32x4 p) {
+  if constexpr (ACT == 0)
+    return f32x4{gelu_grad(p.x), gelu_grad(p.y), gelu_grad(p.z), gelu_grad(p.w)};
+  else
+    return f32x4{p.x > 0.0f ? 1.0f : 0.0f, p.y > 0.0f ? 1.0f : 0.0f, p.z > 0.0f ? 1.0f : 0.0f,
+                 p.w > 0.0f ? 1.0f : 0.0f};
+}
+
+template <int ACT>
 __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
     const float *__restrict__ dh0, const uint16_t *__restrict__ sx, const uint16_t *__restrict__ se1,
     int batch, int nx, int ny, const uint8_t *__restrict__ pack, FragLayout F, BlobLayout L,
@@ -588,9 +602,7 @@ __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
       for (int t = 0; t < 4; ++t) {
         f32x4 p = mfma(w2[t][0], e1[0], b2[t]);
         p = mfma(w2[t][1], e1[1], p);
-        dp2[t] = P.valid ? G[t] * f32x4{gelu_grad(p.x), gelu_grad(p.y), gelu_grad(p.z),
-                                        gelu_grad(p.w)}
-                         : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        dp2[t] = P.valid ? G[t] * act_grad4<ACT>(p) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         s2[t] += dp2[t];
       }
       const u32x4 dpb[2] = {frag_from_acc(dp2[0], dp2[1]), frag_from_acc(dp2[2], dp2[3])};
@@ -601,7 +613,7 @@ __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
                          f32x4{0.0f, 0.0f, 0.0f, 0.0f});
         de1 = mfma(load_frag(frags, F.W2T + 2 * t + 1, lane), dpb[1], de1);
         f32x4 p1 = mfma(load_frag(frags, F.W1 + t, lane), xb, b1[t]);
-        dp1[t] = de1 * f32x4{gelu_grad(p1.x), gelu_grad(p1.y), gelu_grad(p1.z), gelu_grad(p1.w)};
+        dp1[t] = de1 * act_grad4<ACT>(p1);
         s1[t] += dp1[t];
       }
       const int col = 16 * half + n;
@@ -711,7 +723,7 @@ extern "C" int gnn_backward(const float *dL_dgpost, const float *g_pre, const vo
   const int R = n_rounds;
   if (!dL_dgpost || !g_pre || !saved || !tau || !params || !grad)
     return fail(LBM_EINVAL, "gnn_backward: null pointer");
-  if (R < 1 || R > MAX_ROUNDS) return fail(LBM_EINVAL, "gnn_backward: bad n_rounds %d", R);
+  if (R < 0 || R > MAX_ROUNDS) return fail(LBM_EINVAL, "gnn_backward: bad n_rounds %d", R);
   if (batch < 1 || !lbm::lattice_ok(nx, ny) || (long long)batch * nx * ny >= (1LL << 31))
     return fail(LBM_EINVAL, "gnn_backward: bad sizes");
   const long long nodes = (long long)batch * nx * ny;
@@ -752,9 +764,15 @@ extern "C" int gnn_backward(const float *dL_dgpost, const float *g_pre, const vo
     if (int rc = launch_check("bwd_edge_send_kernel")) return rc;
     cur ^= 1;
   }
-  hipLaunchKernelGGL(bwd_encoder_kernel, dim3(kBwdBlocks), dim3(kBT), 0, s, dh[cur],
-                     (const uint16_t *)at(saved, SL.x), (const uint16_t *)at(saved, SL.e1),
-                     batch, nx, ny, pack, F, L, part);
+  // n_rounds = 0 is the per-node network of Fig. 2, which uses ReLU
+  if (R == 0)
+    hipLaunchKernelGGL(bwd_encoder_kernel<1>, dim3(kBwdBlocks), dim3(kBT), 0, s, dh[cur],
+                       (const uint16_t *)at(saved, SL.x), (const uint16_t *)at(saved, SL.e1),
+                       batch, nx, ny, pack, F, L, part);
+  else
+    hipLaunchKernelGGL(bwd_encoder_kernel<0>, dim3(kBwdBlocks), dim3(kBT), 0, s, dh[cur],
+                       (const uint16_t *)at(saved, SL.x), (const uint16_t *)at(saved, SL.e1),
+                       batch, nx, ny, pack, F, L, part);
   if (int rc = launch_check("bwd_encoder_kernel")) return rc;
   hipLaunchKernelGGL(bwd_reduce_kernel, dim3((unsigned)((L.nparam + kBT - 1) / kBT)), dim3(kBT),
                      0, s, part, L.nparam, grad);

@@ -90,12 +90,21 @@ constexpr int kSlot = 12;   // dwords per node: 8 for the features, then 10 head
 
 constexpr int kBlocksPerCu = 5;   // resident blocks (LDS 27 KB, <= 102 registers)
 
-template <bool PULL>
+// What a training forward keeps per node for the backward pass: the BF16
+// operands the MFMAs consumed (features, both hidden layers, fragment order)
+// and the FP32 head outputs; the layout of gnn_forward's saved buffer for
+// zero rounds.
+struct SimpleSave {
+  uint16_t *x, *e1, *h0;
+  float *z;
+};
+
+template <bool PULL, bool SAVE>
 __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int batch, int nx, int ny,
     const float *__restrict__ tau_arr, float tau_s, const uint8_t *__restrict__ pack,
     FragLayout F, float *__restrict__ head_out, double *__restrict__ pmass,
-    unsigned *__restrict__ pflag) {
+    unsigned *__restrict__ pflag, SimpleSave sv) {
   __shared__ u32x4 w_s[14 * 64];   // W1 (4), W2 (8), Wh (2) fragments
   __shared__ f32x4 b_s[9 * 4];     // b1 (4), b2 (4), bh (1), per channel group
   __shared__ __attribute__((aligned(16))) uint32_t slot_s[kWaves][64 * kSlot];
@@ -185,6 +194,19 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
       for (int t = 0; t < 4; ++t)
         a[t] = mfma(w[(5 + 2 * t) * 64], e1[1], mfma(w[(4 + 2 * t) * 64], e1[0], bs[(4 + t) * 4]));
       const u32x4 hb[2] = {relu_frag(a[0], a[1]), relu_frag(a[2], a[3])};
+      if constexpr (SAVE) {
+        const int xs = xc * 64 + 16 * grp + n;
+        if (xs < nx) {
+          const size_t node = ((size_t)b * ny + y) * nx + xs;
+          if (q < 2) ((u32x4 *)(sv.x + node * 16))[q] = xb;
+          u32x4 *de = (u32x4 *)(sv.e1 + node * HID);
+          de[q] = e1[0];
+          de[4 + q] = e1[1];
+          u32x4 *dh = (u32x4 *)(sv.h0 + node * HID);
+          dh[q] = hb[0];
+          dh[4 + q] = hb[1];
+        }
+      }
       const f32x4 z = mfma(w[13 * 64], hb[1], mfma(w[12 * 64], hb[0], bs[8 * 4]));
       // the features of these 16 nodes are consumed (z depends on them):
       // their slots take the head outputs, rows 4q..4q+3
@@ -220,6 +242,11 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
       if (head_out) {
         const size_t node = ((size_t)b * ny + y) * nx + x;
         for (int k = 0; k < NOUT; ++k) head_out[node * NOUT + k] = z[k];
+      }
+      if constexpr (SAVE) {
+        const size_t node = ((size_t)b * ny + y) * nx + x;
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k) sv.z[node * 12 + k] = z[k];
       }
     }
     wave_lds_sync();
@@ -272,7 +299,7 @@ static int simple_device_cus() {
 
 static int launch_simple(bool pull, const float *src, float *dst, int batch, int nx, int ny,
                          const float *tau_arr, float tau, const float *params, float *head_out,
-                         void *ws, hipStream_t s, int &nparts) {
+                         void *saved, void *ws, hipStream_t s, int &nparts) {
   const FragLayout F = frag_layout(0);
   const SimpleScratch W = simple_scratch();
   uint8_t *pack = (uint8_t *)at_(ws, W.pack);
@@ -286,12 +313,25 @@ static int launch_simple(bool pull, const float *src, float *dst, int batch, int
   nparts = nb;
   double *pm = (double *)at_(ws, W.pmass);
   unsigned *pf = (unsigned *)at_(ws, W.pflag);
+  simple::SimpleSave sv{};
+  if (saved) {
+    const SavedLayout SL = saved_layout((long long)batch * nx * ny, 0);
+    sv.x = (uint16_t *)at_(saved, SL.x);
+    sv.e1 = (uint16_t *)at_(saved, SL.e1);
+    sv.h0 = (uint16_t *)at_(saved, SL.h);
+    sv.z = (float *)at_(saved, SL.z);
+  }
   if (pull)
-    hipLaunchKernelGGL(simple::simple_step_kernel<true>, dim3(nb), dim3(simple::kThreads), 0, s,
-                       src, dst, batch, nx, ny, tau_arr, tau, pack, F, head_out, pm, pf);
+    hipLaunchKernelGGL((simple::simple_step_kernel<true, false>), dim3(nb), dim3(simple::kThreads),
+                       0, s, src, dst, batch, nx, ny, tau_arr, tau, pack, F, head_out, pm, pf, sv);
+  else if (saved)
+    hipLaunchKernelGGL((simple::simple_step_kernel<false, true>), dim3(nb),
+                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, pack,
+                       F, head_out, pm, pf, sv);
   else
-    hipLaunchKernelGGL(simple::simple_step_kernel<false>, dim3(nb), dim3(simple::kThreads), 0,
-                       s, src, dst, batch, nx, ny, tau_arr, tau, pack, F, head_out, pm, pf);
+    hipLaunchKernelGGL((simple::simple_step_kernel<false, false>), dim3(nb),
+                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, pack,
+                       F, head_out, pm, pf, sv);
   return launch_check("simple_step_kernel");
 }
 
@@ -304,7 +344,8 @@ static int check_simple(const char *who, int batch, int nx, int ny, const float 
 
 extern "C" int simple_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
                               const float *tau, const float *params, float *head_out,
-                              void *workspace, size_t ws_bytes, void *stream) {
+                              void *saved, size_t saved_bytes, void *workspace,
+                              size_t ws_bytes, void *stream) {
   if (int rc = check_simple("simple_forward", batch, nx, ny, params)) return rc;
   if (!g_pre || !g_post || !tau) return fail(LBM_EINVAL, "simple_forward: null pointer");
   if (lbm::overlap(g_pre, g_post, (size_t)batch * 9 * nx * ny * sizeof(float)))
@@ -312,9 +353,12 @@ extern "C" int simple_forward(const float *g_pre, float *g_post, int batch, int 
   if (!workspace || ws_bytes < simple_scratch().total)
     return fail(LBM_EWORKSPACE, "simple_forward: workspace needs %zu bytes",
                 simple_scratch().total);
+  const size_t saved_need = gnn::saved_bytes(batch, nx, ny, 0);
+  if (saved && saved_bytes < saved_need)
+    return fail(LBM_EWORKSPACE, "simple_forward: saved buffer needs %zu bytes", saved_need);
   if (int rc = check_device()) return rc;
   int nparts = 0;
-  return launch_simple(false, g_pre, g_post, batch, nx, ny, tau, 0.0f, params, head_out,
+  return launch_simple(false, g_pre, g_post, batch, nx, ny, tau, 0.0f, params, head_out, saved,
                        workspace, (hipStream_t)stream, nparts);
 }
 
@@ -335,7 +379,7 @@ extern "C" int lbm_step_simple(const float *g_src, float *g_dst, int nx, int ny,
   hipStream_t s = (hipStream_t)stream;
   int nparts = 0;
   if (int rc = launch_simple(true, g_src, g_dst, 1, nx, ny, nullptr, tau, params, nullptr,
-                             workspace, s, nparts))
+                             nullptr, workspace, s, nparts))
     return rc;
   if (!fb) return LBM_OK;
   const SimpleScratch W = simple_scratch();

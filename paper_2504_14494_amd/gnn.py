@@ -17,7 +17,7 @@ from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
            "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
-           "GnnMse", "simple_forward", "lbm_step_simple", "gnn_gelu_rate"]
+           "GnnMse", "simple_forward", "lbm_step_simple", "gnn_gelu_rate", "collide"]
 
 
 def gnn_param_count(rounds: int = 2) -> int:
@@ -116,9 +116,11 @@ def lbm_step_gnn(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.T
 
 
 def simple_forward(g_pre: torch.Tensor, tau: torch.Tensor, blob: torch.Tensor,
-                   want_z: bool = False, ws: Workspace = None):
+                   want_z: bool = False, saved: torch.Tensor = None, ws: Workspace = None):
     """The per-node (Fig. 2) corrected collision of a batch of pre-collision
-    states, no streaming.  blob: zero-round layout.  Returns (g_post, z)."""
+    states, no streaming.  blob: zero-round layout.  With `saved` (uint8,
+    saved_bytes(B, nx, ny, 0)) the activations gnn_backward(rounds=0) needs
+    are kept.  Returns (g_post, z)."""
     single = g_pre.dim() == 3
     if single:
         g_pre = g_pre.unsqueeze(0)
@@ -132,13 +134,26 @@ def simple_forward(g_pre: torch.Tensor, tau: torch.Tensor, blob: torch.Tensor,
     z = torch.empty((B, ny, nx, 10), dtype=torch.float32, device=g_pre.device) if want_z else None
     L = _lib.load()
     buf = (ws or _ws).get(L.lbm_workspace_bytes(_lib.LBM_WS_SIMPLE, B, nx, ny, 0))
+    if saved is not None:
+        _need(saved, torch.uint8, "saved")
     rc = L.simple_forward(_ptr(g_pre), _ptr(out), B, nx, ny, _ptr(tau), _ptr(blob), _ptr(z),
-                          _ptr(buf), buf.numel(), _stream())
+                          _ptr(saved), 0 if saved is None else saved.numel(), _ptr(buf),
+                          buf.numel(), _stream())
     check(rc, "simple_forward")
     if single:
         out = out[0]
         z = z[0] if z is not None else None
     return out, z
+
+
+def collide(g_pre: torch.Tensor, tau: torch.Tensor, blob: torch.Tensor, rounds: int,
+            want_z: bool = False, saved: torch.Tensor = None):
+    """Corrected collision of a batch of pre-collision states with either
+    network: message passing (rounds >= 1, gnn_forward) or the per-node
+    network of Fig. 2 (rounds = 0, simple_forward).  Returns (g_post, z)."""
+    if rounds == 0:
+        return simple_forward(g_pre, tau, blob, want_z=want_z, saved=saved)
+    return gnn_forward(g_pre, tau, blob, rounds, want_z=want_z, saved=saved)
 
 
 def lbm_step_simple(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.Tensor,
@@ -237,8 +252,9 @@ def backward_ws_bytes(batch: int, nx: int, ny: int, rounds: int = 2) -> int:
 def gnn_backward(dL_dgpost: torch.Tensor, g_pre: torch.Tensor, saved: torch.Tensor,
                  tau: torch.Tensor, blob: torch.Tensor, rounds: int = 2,
                  grad: torch.Tensor = None, ws: Workspace = None) -> torch.Tensor:
-    """dL/dparams (FP32, [gnn_param_count]) of the gnn_forward call that
-    filled `saved` (same g_pre, tau, blob), given dL/dg_post."""
+    """dL/dparams (FP32, [gnn_param_count]) of the forward call that filled
+    `saved` (same g_pre, tau, blob), given dL/dg_post: gnn_forward for
+    rounds >= 1, simple_forward for rounds = 0."""
     if g_pre.dim() == 3:
         g_pre, dL_dgpost = g_pre.unsqueeze(0), dL_dgpost.unsqueeze(0)
     _need(g_pre, torch.float32, "g_pre")
@@ -297,7 +313,8 @@ def gnn_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
 
 class GnnCollide(torch.autograd.Function):
     """torch.autograd face of the corrected collision: forward = gnn_forward
-    (activations saved), backward = gnn_backward (gradient with respect to the
+    (rounds >= 1) or simple_forward (rounds = 0, the Fig. 2 network), with the
+    activations saved; backward = gnn_backward (gradient with respect to the
     parameter blob only; populations and tau are data)."""
 
     @staticmethod
@@ -305,7 +322,10 @@ class GnnCollide(torch.autograd.Function):
         B, nx, ny = _batch_dims(g_pre)
         saved = torch.empty(saved_bytes(B, nx, ny, rounds), dtype=torch.uint8,
                             device=g_pre.device)
-        out, _ = gnn_forward(g_pre, tau, blob.detach(), rounds, saved=saved)
+        if rounds == 0:
+            out, _ = simple_forward(g_pre, tau, blob.detach(), saved=saved)
+        else:
+            out, _ = gnn_forward(g_pre, tau, blob.detach(), rounds, saved=saved)
         ctx.save_for_backward(blob, g_pre, tau)
         ctx.saved_acts = saved
         ctx.rounds = rounds

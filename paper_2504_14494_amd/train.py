@@ -146,7 +146,7 @@ def bgk_loss(X, Y, T, rounds: int, chunk: int = 32) -> float:
     blob = zero_head(torch.as_tensor(inputs.gnn_blob(0, rounds), device=X.device), rounds)
     total, nodes = 0.0, 0
     for s in range(0, X.shape[0], chunk):
-        out, _ = gnn.gnn_forward(X[s:s + chunk], T[s:s + chunk], blob, rounds)
+        out, _ = gnn.collide(X[s:s + chunk], T[s:s + chunk], blob, rounds)
         loss, _ = gnn.gnn_mse(out, Y[s:s + chunk], 1.0, want_grad=False)
         n = out.numel() // 9
         total += loss.item() * n
@@ -157,7 +157,7 @@ def bgk_loss(X, Y, T, rounds: int, chunk: int = 32) -> float:
 def eval_loss(blob, X, Y, T, rounds: int, scale: float, chunk: int = 32) -> float:
     total, nodes = 0.0, 0
     for s in range(0, X.shape[0], chunk):
-        out, _ = gnn.gnn_forward(X[s:s + chunk], T[s:s + chunk], blob, rounds)
+        out, _ = gnn.collide(X[s:s + chunk], T[s:s + chunk], blob, rounds)
         loss, _ = gnn.gnn_mse(out, Y[s:s + chunk], scale, want_grad=False)
         n = out.numel() // 9
         total += loss.item() * n
@@ -196,7 +196,7 @@ class Trainer:
         B, ny, _, nx = xb.shape
         saved = torch.empty(gnn.saved_bytes(B, nx, ny, self.rounds), dtype=torch.uint8,
                             device=xb.device)
-        out, _ = gnn.gnn_forward(xb, tb, self.blob, self.rounds, saved=saved)
+        out, _ = gnn.collide(xb, tb, self.blob, self.rounds, saved=saved)
         loss, dl = gnn.gnn_mse(out, yb, scale)
         grad = gnn.gnn_backward(dl, xb, saved, tb, self.blob, self.rounds)
         self.step_count += 1
@@ -229,30 +229,49 @@ class Trainer:
             self.rng.bit_generator.state = json.loads(bytes(z["rng"]).decode())
 
 
+def datasets(cfg: DataConfig = None, held_out_runs: int = 8, device="cuda"):
+    """Training and held-out pairs: ((X, Y, T), (Xh, Yh, Th))."""
+    cfg = cfg or DataConfig()
+    hcfg = dataclasses.replace(cfg, runs=held_out_runs, seed=cfg.seed + 1)
+    return make_dataset(cfg, device), make_dataset(hcfg, device)
+
+
 def train(cfg: DataConfig = None, steps: int = 2000, batch: int = 32, rounds: int = 2,
           lr: float = 1e-3, init_seed: int = 0, s_delta: float = 1e-4, held_out_runs: int = 8,
-          log_every: int = 0, device="cuda"):
-    """Full training run; returns (trainer, report dict)."""
-    cfg = cfg or DataConfig()
-    X, Y, T = make_dataset(cfg, device)
-    hcfg = dataclasses.replace(cfg, runs=held_out_runs, seed=cfg.seed + 1)
-    Xh, Yh, Th = make_dataset(hcfg, device)
+          log_every: int = 0, device="cuda", data=None):
+    """Full training run; returns (trainer, report dict).  `data` reuses the
+    pairs of datasets() (same cfg and held_out_runs) instead of generating
+    them."""
+    import time
+    t0 = time.perf_counter()
+    if data is None:
+        data = datasets(cfg, held_out_runs, device)
+    (X, Y, T), (Xh, Yh, Th) = data
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
     l_bgk = bgk_loss(X, Y, T, rounds)
     l_bgk_h = bgk_loss(Xh, Yh, Th, rounds)
     blob = torch.as_tensor(inputs.gnn_blob(init_seed, rounds, s_delta=s_delta), device=device)
     tr = Trainer(blob, rounds, lr)
     before = eval_loss(tr.blob, Xh, Yh, Th, rounds, 1.0 / l_bgk_h)
     hist = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     for k in range(steps):
         loss = tr.step(X, Y, T, 1.0 / l_bgk, batch)
         if log_every and (k % log_every == 0 or k == steps - 1):
             hist.append((k, loss.item()))
+    torch.cuda.synchronize()
+    t_opt = time.perf_counter() - t1
     after = eval_loss(tr.blob, Xh, Yh, Th, rounds, 1.0 / l_bgk_h)
     train_after = eval_loss(tr.blob, X, Y, T, rounds, 1.0 / l_bgk)
     return tr, {"bgk_loss_train": l_bgk, "bgk_loss_heldout": l_bgk_h,
                 "heldout_rel_loss_before": before, "heldout_rel_loss_after": after,
                 "train_rel_loss_after": train_after, "history": hist,
-                "samples": int(X.shape[0]), "heldout_samples": int(Xh.shape[0])}
+                "samples": int(X.shape[0]), "heldout_samples": int(Xh.shape[0]),
+                "data_seconds": t_data, "optimizer_seconds": t_opt,
+                # one sample = one 128^2 lattice through forward, Eq. 4, backward
+                "samples_per_s": steps * batch / t_opt if t_opt > 0 else None}
 
 
 def main(argv=None):

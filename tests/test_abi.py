@@ -81,11 +81,12 @@ def test_every_entry_point_rejects_bad_arguments_before_device_work():
         ("lbm_step_gnn", (a, b, 4, 4, 0.7, c, 2, None, d, 16, None), EWORKSPACE),
         ("lbm_step_gnn", (a, b, 4, 4, -1.0, c, 2, None, d, 1 << 30, None), EINVAL),
         ("gnn_forward", (a, a, 1, 4, 4, b, c, 2, None, None, 0, d, 1 << 30, None), EINVAL),
-        ("gnn_backward", (a, b, c, 1, 4, 4, d, e, 0, f, a, 1 << 30, None), EINVAL),
+        ("gnn_backward", (a, b, c, 1, 4, 4, d, e, -1, f, a, 1 << 30, None), EINVAL),
         ("gnn_mse", (a, b, 0, 4, 4, 1.0, c, d, e, 1 << 30, None), EINVAL),
         ("gnn_adam", (a, b, c, d, 16, 1e-3, 0.9, 0.999, 1e-8, 0, None), EINVAL),
         ("lbm_step_simple", (a, b, 4, 4, -1.0, c, None, d, 1 << 30, None), EINVAL),
-        ("simple_forward", (a, a, 1, 4, 4, b, c, None, d, 1 << 30, None), EINVAL),
+        ("simple_forward", (a, a, 1, 4, 4, b, c, None, None, 0, d, 1 << 30, None), EINVAL),
+        ("simple_forward", (a, b, 1, 4, 4, b, c, None, e, 16, d, 1 << 30, None), EWORKSPACE),
     ]
     for name, args, code in cases:
         rc = getattr(L, name)(*args)

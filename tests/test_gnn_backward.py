@@ -145,3 +145,41 @@ def test_adam_steps_lower_the_loss_on_a_fixed_batch():
         gnn.gnn_adam(blob, grad, m, v, step, lr=1e-3)
     print("loss:", losses[0], "->", losses[-1])
     assert losses[-1] < 0.75 * losses[0]
+
+
+def _gpu_grad_fig2(g_planes, G_planes, taus, blob):
+    g = _dev(inputs.planes_to_rows(g_planes))
+    G = _dev(inputs.planes_to_rows(G_planes))
+    B, _, ny, nx = g_planes.shape
+    saved = torch.empty(gnn.saved_bytes(B, nx, ny, 0), dtype=torch.uint8, device="cuda")
+    t, b = _dev(taus), _dev(blob)
+    out, _ = gnn.simple_forward(g, t, b, saved=saved)
+    grad = gnn.gnn_backward(G, g, saved, t, b, 0)
+    torch.cuda.synchronize()
+    return out, grad.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("B,ny,nx,sd", [(2, 12, 20, 1.0), (1, 17, 70, 1e-2), (1, 3, 4, 1.0)])
+def test_fig2_backward_matches_oracle_gradient(orc, B, ny, nx, sd):
+    """The per-node ReLU network of Fig. 2 (zero rounds): saving forward of
+    the fused kernel, head backward, encoder backward with the ReLU
+    derivative, against the oracle's exact gradient of the same network."""
+    g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=300 + nx)
+    G = inputs.random_shifted_state((B, 9, ny, nx), 1.0, seed=400 + nx)
+    taus = np.float32(0.6 + 0.1 * np.arange(B))
+    blob = inputs.gnn_blob(13, 0, s_delta=sd)
+    out, got = _gpu_grad_fig2(g, G, taus, blob)
+    ref = orc.gnn_backward(g.astype(np.float64) + _w(orc)[None], G.astype(np.float64),
+                           taus.astype(np.float64), blob.astype(np.float64), 0, mode=1, act=1)
+    worst = {}
+    for name, (o, shp) in inputs.blob_offsets(0).items():
+        if name in ("mu", "sigma", "s_delta"):
+            continue
+        k = int(np.prod(shp))
+        worst[name] = _rel(got[o:o + k], ref[o:o + k])
+    print("per-tensor rel-L2:", {k: f"{v:.1e}" for k, v in worst.items()})
+    assert max(worst.values()) <= 2e-2, worst
+    assert _rel(got, ref) <= 1e-2
+    # the saving forward is the inference forward
+    ref_out, _ = gnn.simple_forward(_dev(inputs.planes_to_rows(g)), _dev(taus), _dev(blob))
+    assert torch.equal(out, ref_out)

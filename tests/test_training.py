@@ -68,3 +68,15 @@ def test_trained_collision_beats_bgk_on_held_out_flows():
     assert rep["heldout_rel_loss_before"] > 0.5
     assert rep["heldout_rel_loss_after"] < 1.0
     assert rep["train_rel_loss_after"] < 1.0
+
+
+def test_trained_fig2_network_beats_bgk_on_held_out_flows():
+    """The same training (Eq. 4 relative to BGK, Adam) of the paper's Fig. 2
+    network: per-node ReLU MLP, zero rounds, fused forward with saved
+    activations and the zero-round backward."""
+    tr, rep = train.train(_small_cfg(), steps=300, batch=16, rounds=0, held_out_runs=4,
+                          log_every=50)
+    print({k: v for k, v in rep.items() if k != "history"}, rep["history"])
+    assert rep["heldout_rel_loss_before"] > 0.5
+    assert rep["heldout_rel_loss_after"] < 1.0
+    assert rep["train_rel_loss_after"] < 1.0
