@@ -336,3 +336,47 @@ def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
                      "slip_rel_closed_form": float(slip / ua.max()),
                      "seconds": t0.elapsed_time(t1) * 1e-3})
     return {"ny": ny, "nx": nx, "u_max": u_max, "fp64": fp64, "rows": rows}
+
+
+def main(argv=None):
+    """Runs one study and prints its report as JSON:
+    python -m paper_2504_14494_amd.experiments {fixed-error, resolution,
+    stability, poiseuille, long-rollout} [--rounds R].  The corrected-collision
+    studies first train the network (train.train, full configuration)."""
+    import argparse
+    import json
+    import time
+
+    from . import train
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["fixed-error", "resolution", "stability", "poiseuille",
+                                      "long-rollout"])
+    ap.add_argument("--rounds", type=int, default=2, help="2: message passing; 0: Fig. 2")
+    ap.add_argument("--scaling", default="diffusive", choices=["diffusive", "acoustic"])
+    ap.add_argument("--fp64", action="store_true", help="BGK runs in FP64 (resolution, poiseuille)")
+    ap.add_argument("--steps", type=int, default=20000, help="long-rollout steps")
+    args = ap.parse_args(argv)
+    t0 = time.perf_counter()
+    blob = None
+    if args.study in ("fixed-error", "stability", "long-rollout") or (
+            args.study == "resolution" and not args.fp64):
+        tr, rep = train.train(train.DataConfig(), steps=2000, batch=32, rounds=args.rounds)
+        blob = tr.blob
+    if args.study == "fixed-error":
+        out = fixed_error_report(blob, rounds=args.rounds)
+    elif args.study == "resolution":
+        out = {"bgk": resolution_study(None, scaling=args.scaling, fp64=args.fp64)}
+        if blob is not None:
+            out["gnn"] = resolution_study(blob, rounds=args.rounds, scaling=args.scaling)
+    elif args.study == "stability":
+        out = stability_sweep(blob, rounds=args.rounds)
+    elif args.study == "poiseuille":
+        out = poiseuille_study(fp64=args.fp64)
+    else:
+        out = long_rollout(blob, rounds=args.rounds, steps=args.steps)
+    out["wall_seconds"] = round(time.perf_counter() - t0, 1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

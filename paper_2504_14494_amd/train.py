@@ -90,8 +90,7 @@ def run_pairs(u0: float, re: float, phase, cfg: DataConfig, device="cuda"):
     plain-BGK run of the same flow with the same target.  The coarse states
     carry the coarse lattice's own non-hydrodynamic content, which a corrected
     coarse run meets and restricted fine states never show."""
-    nf, fac = cfg.n_fine, cfg.factor
-    nc = nf // fac
+    nf, fac, nc = cfg.n_fine, cfg.factor, cfg.n_coarse
     tau_f, tau_c = taus(u0, re, nf, fac)
     lat = lbm.Lattice(nf, nf, dtype=torch.float64, device=device).init_ce(
         *tgv_fields(nf, u0, phase), tau_f)
