@@ -399,6 +399,19 @@ def main():
         "roofline": roof,
         "tgv_l2_err_bgk": bgk["tgv_l2_err"],
     }
+    if args.n == 8192:
+        # the other BGK throughput configurations: 4096^2 and 8192^2 at
+        # Re = 100, 1000, 5000 (throughput does not depend on Re; each run
+        # also checks that the state stays finite and mass-conserving)
+        sweep = []
+        for n in (4096, 8192):
+            for re in (100.0, 1000.0, 5000.0):
+                r = bgk_leg(n, re, 0.04, 200, 20)
+                sweep.append({"n": n, "re": re, "tau": round(r["tau"], 5),
+                              "mlups": round(r["mlups"], 1),
+                              "finite": bool(r["tgv_l2_err"] == r["tgv_l2_err"]),
+                              "mass_drift": r["mass_drift"]})
+        out["bgk_configs"] = sweep
     if not args.no_gnn:
         try:
             g = gnn_leg(2048, args.gnn_steps, 3)
