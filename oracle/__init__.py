@@ -78,6 +78,8 @@ def lib():
         L.orc_gnn_collide.restype = i
         L.orc_gnn_collide_act.argtypes = [pd, pd, i, i, i, pd, pd, i, i, i, pd]
         L.orc_gnn_collide_act.restype = i
+        L.orc_gnn_collide_forced.argtypes = [pd, pd, i, i, i, pd, pd, i, i, i, d, pd]
+        L.orc_gnn_collide_forced.restype = i
         L.orc_gnn_backward_act.argtypes = [pd, pd, i, i, i, pd, pd, i, i, i, pd]
         L.orc_gnn_backward_act.restype = i
         L.orc_gnn_collide_nodes.argtypes = [pd, i, i, d, pd, i, i,
@@ -257,10 +259,12 @@ def project(v) -> np.ndarray:
 
 
 def gnn_collide(f, tau, blob, rounds: int = 2, mode: int = 0,
-                want_z: bool = False, act: int = 0):
+                want_z: bool = False, act: int = 0, gx: float = 0.0):
     """GNN-corrected collision (Eq. 3) of pre-collision f ([9,ny,nx] or
     [B,9,ny,nx]).  mode 0 = FP64, 1 = BF16 storage emulation; act 0 = GELU,
-    1 = ReLU (with rounds = 0: the per-node network of the paper's Fig. 2)."""
+    1 = ReLU (with rounds = 0: the per-node network of the paper's Fig. 2);
+    gx != 0: under a body force rho * gx along x (Guo's velocity and source
+    at the effective relaxation time tau * tau_adj)."""
     f = _f64(f)
     single = f.ndim == 3
     if single:
@@ -271,8 +275,13 @@ def gnn_collide(f, tau, blob, rounds: int = 2, mode: int = 0,
     assert blob.size == blob_len(rounds)
     out = np.empty_like(f)
     z = np.zeros((B, ny, nx, NOUT)) if want_z else None
-    rc = lib().orc_gnn_collide_act(_p(f), _p(out), B, nx, ny, _p(tau), _p(blob),
-                                   rounds, mode, act, _p(z) if want_z else None)
+    if gx == 0.0:
+        rc = lib().orc_gnn_collide_act(_p(f), _p(out), B, nx, ny, _p(tau), _p(blob),
+                                       rounds, mode, act, _p(z) if want_z else None)
+    else:
+        rc = lib().orc_gnn_collide_forced(_p(f), _p(out), B, nx, ny, _p(tau),
+                                          _p(blob), rounds, mode, act, gx,
+                                          _p(z) if want_z else None)
     if rc:
         raise MemoryError("oracle forward could not allocate")
     if single:

@@ -352,3 +352,84 @@ def test_fallback_rule(orc):
     # a wrong previous mass trips the drift test
     _, flags, _ = orc.gnn_collide_gated(f, tau, blob, 1e-6, mass * (1 + 1e-5))
     assert flags == 2
+
+
+# ------------------------------------------- corrected collision under a force ---
+# Reading: the paper names no forcing scheme for its network; under a body
+# force rho * gx the node velocity is Guo's u = (sum e f + F/2) / rho, which
+# the features and f^eq use, and Guo's source is added at the effective
+# relaxation time tau * tau_adj.
+
+GX = 3e-4
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("rounds,act", [(2, 0), (0, 1)])
+def test_forced_zero_head_is_the_forced_bgk_collision(orc, mode, rounds, act):
+    f = _state(orc, (9, 6, 7), 31)
+    blob = _blob(11, rounds=rounds)
+    _set(blob, "Wh", 0.0, rounds)
+    _set(blob, "bh", 0.0, rounds)
+    out = orc.gnn_collide(f, 0.7, blob, rounds=rounds, mode=mode, act=act, gx=GX)
+    assert np.abs(out - orc.collide_forced(f, 0.7, GX)).max() < 1e-16
+
+
+def test_forced_tau_head_relaxes_and_forces_at_the_effective_time(orc):
+    f = _state(orc, (9, 5, 5), 32)
+    blob = _blob(12, rounds=0)
+    beta = -0.6
+    _set(blob, "Wh", 0.0, 0)
+    bh = np.zeros(10)
+    bh[0] = beta
+    _set(blob, "bh", bh, 0)
+    out = orc.gnn_collide(f, 0.8, blob, rounds=0, act=1, gx=GX)
+    tau_eff = 0.8 * (0.5 + 1 / (1 + np.exp(-beta)))
+    assert np.abs(out - orc.collide_forced(f, tau_eff, GX)).max() < 1e-16
+
+
+def test_forced_population_head_adds_the_projected_correction(orc):
+    ex, ey, _ = orc.lattice()
+    f = _state(orc, (9, 4, 6), 33)
+    blob = _blob(13, s_delta=0.01, rounds=0)
+    v = np.linspace(1, -1, 9) ** 3
+    _set(blob, "Wh", 0.0, 0)
+    _set(blob, "bh", np.concatenate([[0.0], v]), 0)
+    out = orc.gnn_collide(f, 0.9, blob, rounds=0, act=1, gx=GX)
+    pv = v - (v.sum() / 9 + ex * (ex @ v) / 6 + ey * (ey @ v) / 6)
+    sd = blob[inputs.blob_offsets(0)["s_delta"][0]]
+    expect = orc.collide_forced(f, 0.9, GX) + sd * pv[:, None, None]
+    assert np.abs(out - expect).max() < 1e-16
+
+
+@pytest.mark.parametrize("rounds,act", [(2, 0), (0, 1)])
+def test_forced_collision_keeps_mass_and_adds_the_force(orc, rounds, act):
+    ex, ey, _ = orc.lattice()
+    f = _state(orc, (9, 6, 6), 34)
+    out = orc.gnn_collide(f, 0.6, _blob(14, s_delta=1e-2, rounds=rounds), rounds=rounds,
+                          act=act, gx=GX)
+    rho = f.sum(0)
+    assert np.abs(out.sum(0) - rho).max() < 1e-15
+    assert np.abs(np.tensordot(ex, out - f, 1) - rho * GX).max() < 1e-15
+    assert np.abs(np.tensordot(ey, out - f, 1)).max() < 1e-15
+    # a different function from the unforced collision
+    assert np.abs(out - orc.gnn_collide(f, 0.6, _blob(14, s_delta=1e-2, rounds=rounds),
+                                        rounds=rounds, act=act)).max() > 1e-5
+
+
+def test_forced_features_see_the_half_force_velocity(orc):
+    """A network whose head output z0 is the normalised x-velocity feature
+    (plus a constant keeping the ReLUs open) reads Guo's velocity."""
+    f = _state(orc, (9, 4, 5), 35)
+    blob = _blob(15, rounds=0)
+    W1 = np.zeros((64, 12)); W1[0, 10] = 1.0
+    W2 = np.zeros((64, 64)); W2[0, 0] = 1.0
+    b1 = np.zeros(64); b1[0] = 20.0
+    Wh = np.zeros((10, 64)); Wh[0, 0] = 1.0
+    for k, val in (("W1", W1), ("b1", b1), ("W2", W2), ("b2", 0.0), ("Wh", Wh),
+                   ("bh", 0.0)):
+        _set(blob, k, val, 0)
+    off_mu = inputs.blob_offsets(0)["mu"][0]
+    mu, sigma = blob[off_mu + 10], blob[off_mu + 12 + 10]
+    _, z = orc.gnn_collide(f, 0.7, blob, rounds=0, act=1, want_z=True, gx=GX)
+    ux, _ = orc.channel_velocity(f, GX)
+    assert np.abs(z[..., 0] - ((ux - mu) / sigma + 20.0)).max() < 1e-12
