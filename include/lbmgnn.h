@@ -252,6 +252,19 @@ int gnn_backward(const float *dL_dgpost, const float *g_pre, const void *saved,
 int lbm_step_simple(const float *g_src, float *g_dst, int nx, int ny, float tau,
                     const float *params, const lbm_fallback *fb, void *workspace,
                     size_t ws_bytes, void *stream);
+/* lbm_step_simple on the channel of lbm_step_channel (validation section,
+ * "Poiseuille Flow"): halfway bounce-back walls below row 0 and above row
+ * ny - 1, x periodic, body force rho * gx along x.  The network reads Guo's
+ * velocity u = (sum e f + F / 2) / rho among its features, f^eq is taken at
+ * that velocity, and Guo's source is added at the network's effective
+ * relaxation time tau * tau_adj (the paper names no forcing scheme for its
+ * network).  The fallback, when fb is given, is the forced BGK channel step
+ * of lbm_step_channel.  gx must be finite (LBM_EINVAL otherwise); other
+ * arguments and errors as for lbm_step_simple. */
+int lbm_step_simple_channel(const float *g_src, float *g_dst, int nx, int ny,
+                            float tau, float gx, const float *params,
+                            const lbm_fallback *fb, void *workspace,
+                            size_t ws_bytes, void *stream);
 /* The same collision alone (no streaming) on a batch of pre-collision states
  * [batch][ny][9][nx], tau: device float[batch]; head_out NULL or
  * [batch][ny][nx][10].  saved: NULL for inference, else a device buffer of

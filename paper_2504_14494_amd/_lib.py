@@ -26,7 +26,7 @@ EXPORTS = [
     "lbm_step_channel", "lbm_step_channel_f64", "lbm_channel_profile",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
     "lbm_step_gnn", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
-    "lbm_step_simple", "simple_forward", "gnn_gelu_rate",
+    "lbm_step_simple", "lbm_step_simple_channel", "simple_forward", "gnn_gelu_rate",
     "lbm_workspace_bytes",
 ]
 
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
         "gnn_mse": ([vp, vp, i, i, i, d, vp, vp, vp, sz, vp], i),
         "gnn_adam": ([vp, vp, vp, vp, sz, f, f, f, f, i, vp], i),
         "lbm_step_simple": ([vp, vp, i, i, f, vp, ctypes.POINTER(LbmFallback), vp, sz, vp], i),
+        "lbm_step_simple_channel": ([vp, vp, i, i, f, f, vp, ctypes.POINTER(LbmFallback), vp, sz,
+                                     vp], i),
         "simple_forward": ([vp, vp, i, i, i, vp, vp, vp, vp, sz, vp, sz, vp], i),
         "lbm_workspace_bytes": ([i, i, i, i, i], sz),
     }

@@ -11,51 +11,11 @@
 // x stays periodic.  Same storage as the periodic step: row-interleaved
 // g[y][i][x] of shifted populations g = f - w; bounce-back swaps directions
 // of equal weight, so it acts on g exactly as on f.
-#include "lbm_common.hpp"
+#include "channel_common.hpp"
 
 namespace lbm {
 
 constexpr int kChannelThreads = 256;
-
-// Pull gather with halfway bounce-back at the two walls:
-// g_i(x, y) = src_i(x - cx_i, y - cy_i) when row y - cy_i lies in the
-// channel, else src_opp(i)(x, y).  Opposite pairs: (1,3) (2,4) (5,7) (6,8).
-template <typename T>
-__device__ __forceinline__ void pull9_walls(const T *__restrict__ src, int nx, int ny, int x,
-                                            int y, T (&g)[9]) {
-  const int xm = x == 0 ? nx - 1 : x - 1;
-  const int xp = x == nx - 1 ? 0 : x + 1;
-  const T *r0 = src + (size_t)y * 9 * nx;
-  const bool below = y > 0, above = y < ny - 1;
-  const T *rm = below ? r0 - (size_t)9 * nx : r0;
-  const T *rp = above ? r0 + (size_t)9 * nx : r0;
-  g[0] = r0[x];
-  g[1] = r0[(size_t)1 * nx + xm];
-  g[3] = r0[(size_t)3 * nx + xp];
-  g[2] = below ? rm[(size_t)2 * nx + x] : r0[(size_t)4 * nx + x];
-  g[5] = below ? rm[(size_t)5 * nx + xm] : r0[(size_t)7 * nx + x];
-  g[6] = below ? rm[(size_t)6 * nx + xp] : r0[(size_t)8 * nx + x];
-  g[4] = above ? rp[(size_t)4 * nx + x] : r0[(size_t)2 * nx + x];
-  g[7] = above ? rp[(size_t)7 * nx + xp] : r0[(size_t)5 * nx + x];
-  g[8] = above ? rp[(size_t)8 * nx + xm] : r0[(size_t)6 * nx + x];
-}
-
-// BGK collision with Guo's body-force term, force rho * gx along x.
-template <typename T>
-__device__ __forceinline__ void forced_collide(T (&g)[9], T omega, T gx) {
-  T drho, rho, u, v, uu;
-  node_moments(g, drho, rho, u, v, uu);
-  u += T(0.5) * gx;
-  uu = u * u + v * v;
-  const T fx = rho * gx;
-  const T src_scale = T(1) - T(0.5) * omega;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T eu = T(cx(i)) * u + T(cy(i)) * v;
-    const T s = wgt<T>(i) * fx * (T(3) * (T(cx(i)) - u) + T(9) * eu * T(cx(i)));
-    g[i] = g[i] + omega * (geq_shifted<T>(i, drho, rho, u, v, uu) - g[i]) + src_scale * s;
-  }
-}
 
 template <typename T>
 __global__ __launch_bounds__(kChannelThreads) void channel_pull_kernel(

@@ -22,6 +22,7 @@
 // the message sum and everything after the head run in FP32 on the VALU.
 #include <cstdio>
 
+#include "channel_common.hpp"
 #include "gnn_common.hpp"
 #include "lbm_common.hpp"
 
@@ -593,10 +594,11 @@ __global__ __launch_bounds__(kThreads) void gate_decide_kernel(
 }
 
 // Plain BGK step from the unchanged source when the gate tripped (same
-// arithmetic as bgk_pull_kernel, grid-stride); exits at once otherwise.
+// arithmetic as bgk_pull_kernel, grid-stride; for the channel, the same as
+// channel_pull_kernel: walls and forcing); exits at once otherwise.
 __global__ __launch_bounds__(kThreads) void gate_fallback_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, float omega,
-    const unsigned *__restrict__ ctrl, double *__restrict__ pmass2) {
+    int walls, float gx, const unsigned *__restrict__ ctrl, double *__restrict__ pmass2) {
   __shared__ double sm[kThreads];
   if (ctrl[0] == 0) return;
   double m = 0.0;
@@ -605,8 +607,13 @@ __global__ __launch_bounds__(kThreads) void gate_fallback_kernel(
        k += (size_t)gridDim.x * kThreads) {
     int x = (int)(k % nx), y = (int)(k / nx);
     float g[9];
-    lbm::pull9(src, nx, ny, x, y, g);
-    lbm::bgk_collide(g, omega);
+    if (walls) {
+      lbm::pull9_walls(src, nx, ny, x, y, g);
+      lbm::forced_collide(g, omega, gx);
+    } else {
+      lbm::pull9(src, nx, ny, x, y, g);
+      lbm::bgk_collide(g, omega);
+    }
     float *d = dst + (size_t)y * 9 * nx + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -774,9 +781,9 @@ namespace gnn {
 // The per-step fallback gate after a corrected step whose workgroups left
 // nparts FP64 mass partials and flag words: decide, recompute with plain BGK
 // if tripped (the kernel exits at once otherwise), and update the mass.
-int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau,
-                const lbm_fallback *fb, int nparts, void *pmass, void *pflag, void *pmass2,
-                void *ctrl, hipStream_t s) {
+int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau, int walls,
+                float gx, const lbm_fallback *fb, int nparts, void *pmass, void *pflag,
+                void *pmass2, void *ctrl, hipStream_t s) {
   double nodes = (double)nx * ny;
   hipLaunchKernelGGL(gate_decide_kernel, dim3(1), dim3(kThreads), 0, s, (const double *)pmass,
                      (const unsigned *)pflag, nparts, nodes, fb->drift_threshold, fb->flags,
@@ -785,7 +792,7 @@ int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau,
   long long fbn = ((long long)nx * ny + kThreads - 1) / kThreads;
   int fbb = (int)(fbn < kMaxGnnBlocks ? fbn : kMaxGnnBlocks);
   hipLaunchKernelGGL(gate_fallback_kernel, dim3(fbb), dim3(kThreads), 0, s, g_src, g_dst, nx, ny,
-                     1.0f / tau, (const unsigned *)ctrl, (double *)pmass2);
+                     1.0f / tau, walls, gx, (const unsigned *)ctrl, (double *)pmass2);
   if (int rc = launch_check("gate_fallback_kernel")) return rc;
   hipLaunchKernelGGL(gate_mass_kernel, dim3(1), dim3(kThreads), 0, s, (const double *)pmass2,
                      fbb, nodes, (const unsigned *)ctrl, fb->mass);
@@ -847,6 +854,6 @@ extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, fl
     return rc;
   if (!fb) return LBM_OK;
   const ForwardScratch W = forward_scratch((long long)nx * ny);
-  return launch_gate(g_src, g_dst, nx, ny, tau, fb, nparts, at(workspace, W.pmass),
+  return launch_gate(g_src, g_dst, nx, ny, tau, 0, 0.0f, fb, nparts, at(workspace, W.pmass),
                      at(workspace, W.pflag), at(workspace, W.pmass2), at(workspace, W.ctrl), s);
 }

@@ -15,6 +15,7 @@
 // shared with the message-passing step; the collision epilogue is this
 // file's own, with the same arithmetic except the hardware exp2 and
 // reciprocal in the sigmoid and the relaxation rate.
+#include "channel_common.hpp"
 #include "gnn_common.hpp"
 #include "lbm_common.hpp"
 
@@ -50,11 +51,18 @@ __device__ __forceinline__ u32x4 relu_frag(f32x4 lo, f32x4 hi) {
 
 // Eq. 3 with the projected correction at one node.  The sigmoid and the
 // relaxation rate use the hardware exp2 and reciprocal (about 1 ulp each);
-// z0 = 0 still gives tau_adj = 1 exactly (2^0 = 1, 1/2 = 0.5).
+// z0 = 0 still gives tau_adj = 1 exactly (2^0 = 1, 1/2 = 0.5).  FORCED: under
+// the channel's body force rho * gx, f^eq is taken at Guo's velocity and
+// Guo's source is added at the effective rate omega = 1 / (tau tau_adj).
+template <bool FORCED>
 __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], float tau,
-                                        float sdelta) {
+                                        float sdelta, float gx) {
   float drho, rho, u, v, uu;
   lbm::node_moments(g, drho, rho, u, v, uu);
+  if constexpr (FORCED) {
+    u += 0.5f * gx;
+    uu = u * u + v * v;
+  }
   constexpr float kLog2e = 1.4426950408889634f;
   float sig = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z[0] * kLog2e));
   float tau_adj = 0.5f + sig;
@@ -72,6 +80,8 @@ __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], f
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     float relaxed = g[i] + omega * (lbm::geq_shifted<float>(i, drho, rho, u, v, uu) - g[i]);
+    if constexpr (FORCED)
+      relaxed += (1.0f - 0.5f * omega) * lbm::guo_source<float>(i, rho * gx, u, v);
     float df = z[1 + i] - m0 - float(cx(i)) * mx - float(cy(i)) * my;
     g[i] = relaxed + sdelta * df;
   }
@@ -99,10 +109,12 @@ struct SimpleSave {
   float *z;
 };
 
-template <bool PULL, bool SAVE>
+// WALLS (with PULL): the channel step, halfway bounce-back at rows 0 and
+// ny - 1 and the body force rho * gx along x.
+template <bool PULL, bool SAVE, bool WALLS>
 __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int batch, int nx, int ny,
-    const float *__restrict__ tau_arr, float tau_s, const uint8_t *__restrict__ pack,
+    const float *__restrict__ tau_arr, float tau_s, float gx, const uint8_t *__restrict__ pack,
     FragLayout F, float *__restrict__ head_out, double *__restrict__ pmass,
     unsigned *__restrict__ pflag, SimpleSave sv) {
   __shared__ u32x4 w_s[14 * 64];   // W1 (4), W2 (8), Wh (2) fragments
@@ -158,7 +170,16 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
           // g_i(x, y) = post_i(x - c_ix, y - c_iy)
           const float *r = cy(i) > 0 ? r0 : (cy(i) < 0 ? r2 : r1);
           const int xsrc = cx(i) > 0 ? xs0 : (cx(i) < 0 ? xs2 : xv);
-          gp[i] = r[i * nx + xsrc];
+          if constexpr (WALLS) {
+            // a population that would come through a wall is the reversed one
+            // that left this node (the row is uniform over the wave)
+            if ((cy(i) > 0 && y == 0) || (cy(i) < 0 && y == ny - 1))
+              gp[i] = r1[lbm::opp(i) * nx + xv];
+            else
+              gp[i] = r[i * nx + xsrc];
+          } else {
+            gp[i] = r[i * nx + xsrc];
+          }
         } else {
           gp[i] = r1[i * nx + xv];
         }
@@ -167,6 +188,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     {
       float drho, rho, u, v, uu;
       lbm::node_moments(gp, drho, rho, u, v, uu);
+      if constexpr (WALLS) u += 0.5f * gx;
       const float raw[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
                                 gp[6], gp[7], gp[8], drho, u,     v};
       float ft[NFEAT];
@@ -224,7 +246,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
         for (int k = 0; k < NOUT; ++k) z[k] = zz[k];
       }
       const float tau = tau_arr ? tau_arr[b] : tau_s;  // b < batch while cw.more()
-      collide(gp, z, tau, sdelta);
+      collide<WALLS>(gp, z, tau, sdelta, gx);
       float *d = dst + (size_t)b * ny * row + (size_t)y * row + x;
       // node mass in FP32 (rounding ~1e-9 per node, ~1e-13 of the lattice
       // mass), accumulated over the nodes in FP64
@@ -275,9 +297,9 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
 }  // namespace simple
 
 // Gate kernels of the message-passing step (gnn_kernels.hip).
-int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau,
-                const lbm_fallback *fb, int nparts, void *pmass, void *pflag, void *pmass2,
-                void *ctrl, hipStream_t s);
+int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau, int walls,
+                float gx, const lbm_fallback *fb, int nparts, void *pmass, void *pflag,
+                void *pmass2, void *ctrl, hipStream_t s);
 
 }  // namespace gnn
 
@@ -297,9 +319,12 @@ static int simple_device_cus() {
   return v;
 }
 
-static int launch_simple(bool pull, const float *src, float *dst, int batch, int nx, int ny,
-                         const float *tau_arr, float tau, const float *params, float *head_out,
-                         void *saved, void *ws, hipStream_t s, int &nparts) {
+// pull: the fused step (else the forward of pre-collision states); walls: the
+// channel step (with pull), body force rho * gx along x.
+static int launch_simple(bool pull, bool walls, float gx, const float *src, float *dst,
+                         int batch, int nx, int ny, const float *tau_arr, float tau,
+                         const float *params, float *head_out, void *saved, void *ws,
+                         hipStream_t s, int &nparts) {
   const FragLayout F = frag_layout(0);
   const SimpleScratch W = simple_scratch();
   uint8_t *pack = (uint8_t *)at_(ws, W.pack);
@@ -321,17 +346,22 @@ static int launch_simple(bool pull, const float *src, float *dst, int batch, int
     sv.h0 = (uint16_t *)at_(saved, SL.h);
     sv.z = (float *)at_(saved, SL.z);
   }
-  if (pull)
-    hipLaunchKernelGGL((simple::simple_step_kernel<true, false>), dim3(nb), dim3(simple::kThreads),
-                       0, s, src, dst, batch, nx, ny, tau_arr, tau, pack, F, head_out, pm, pf, sv);
+  if (pull && walls)
+    hipLaunchKernelGGL((simple::simple_step_kernel<true, false, true>), dim3(nb),
+                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, gx,
+                       pack, F, head_out, pm, pf, sv);
+  else if (pull)
+    hipLaunchKernelGGL((simple::simple_step_kernel<true, false, false>), dim3(nb),
+                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
+                       pack, F, head_out, pm, pf, sv);
   else if (saved)
-    hipLaunchKernelGGL((simple::simple_step_kernel<false, true>), dim3(nb),
-                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, pack,
-                       F, head_out, pm, pf, sv);
+    hipLaunchKernelGGL((simple::simple_step_kernel<false, true, false>), dim3(nb),
+                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
+                       pack, F, head_out, pm, pf, sv);
   else
-    hipLaunchKernelGGL((simple::simple_step_kernel<false, false>), dim3(nb),
-                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, pack,
-                       F, head_out, pm, pf, sv);
+    hipLaunchKernelGGL((simple::simple_step_kernel<false, false, false>), dim3(nb),
+                       dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
+                       pack, F, head_out, pm, pf, sv);
   return launch_check("simple_step_kernel");
 }
 
@@ -358,32 +388,50 @@ extern "C" int simple_forward(const float *g_pre, float *g_post, int batch, int 
     return fail(LBM_EWORKSPACE, "simple_forward: saved buffer needs %zu bytes", saved_need);
   if (int rc = check_device()) return rc;
   int nparts = 0;
-  return launch_simple(false, g_pre, g_post, batch, nx, ny, tau, 0.0f, params, head_out, saved,
+  return launch_simple(false, false, 0.0f, g_pre, g_post, batch, nx, ny, tau, 0.0f, params,
+                       head_out, saved,
                        workspace, (hipStream_t)stream, nparts);
+}
+
+// The fused step, periodic (walls = 0) or the channel (walls = 1, force gx).
+static int step_simple(const char *who, const float *g_src, float *g_dst, int nx, int ny,
+                       float tau, bool walls, float gx, const float *params,
+                       const lbm_fallback *fb, void *workspace, size_t ws_bytes, void *stream) {
+  if (int rc = check_simple(who, 1, nx, ny, params)) return rc;
+  if (!g_src || !g_dst) return fail(LBM_EINVAL, "%s: null pointer", who);
+  if (!(tau > 0.0f)) return fail(LBM_EINVAL, "%s: tau must be positive", who);
+  if (walls && !(gx == gx && fabsf(gx) < INFINITY))
+    return fail(LBM_EINVAL, "%s: force must be finite", who);
+  if (lbm::overlap(g_src, g_dst, (size_t)9 * nx * ny * sizeof(float)))
+    return fail(LBM_EINVAL, "%s: source and destination overlap", who);
+  if (fb && (!fb->flags || !fb->mass))
+    return fail(LBM_EINVAL, "%s: fallback needs flags and mass pointers", who);
+  if (!workspace || ws_bytes < simple_scratch().total)
+    return fail(LBM_EWORKSPACE, "%s: workspace needs %zu bytes", who, simple_scratch().total);
+  if (int rc = check_device()) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int nparts = 0;
+  if (int rc = launch_simple(true, walls, gx, g_src, g_dst, 1, nx, ny, nullptr, tau, params,
+                             nullptr, nullptr, workspace, s, nparts))
+    return rc;
+  if (!fb) return LBM_OK;
+  const SimpleScratch W = simple_scratch();
+  return launch_gate(g_src, g_dst, nx, ny, tau, walls ? 1 : 0, gx, fb, nparts,
+                     at_(workspace, W.pmass), at_(workspace, W.pflag), at_(workspace, W.pmass2),
+                     at_(workspace, W.ctrl), s);
 }
 
 extern "C" int lbm_step_simple(const float *g_src, float *g_dst, int nx, int ny, float tau,
                                const float *params, const lbm_fallback *fb, void *workspace,
                                size_t ws_bytes, void *stream) {
-  if (int rc = check_simple("lbm_step_simple", 1, nx, ny, params)) return rc;
-  if (!g_src || !g_dst) return fail(LBM_EINVAL, "lbm_step_simple: null pointer");
-  if (!(tau > 0.0f)) return fail(LBM_EINVAL, "lbm_step_simple: tau must be positive");
-  if (lbm::overlap(g_src, g_dst, (size_t)9 * nx * ny * sizeof(float)))
-    return fail(LBM_EINVAL, "lbm_step_simple: source and destination overlap");
-  if (fb && (!fb->flags || !fb->mass))
-    return fail(LBM_EINVAL, "lbm_step_simple: fallback needs flags and mass pointers");
-  if (!workspace || ws_bytes < simple_scratch().total)
-    return fail(LBM_EWORKSPACE, "lbm_step_simple: workspace needs %zu bytes",
-                simple_scratch().total);
-  if (int rc = check_device()) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  int nparts = 0;
-  if (int rc = launch_simple(true, g_src, g_dst, 1, nx, ny, nullptr, tau, params, nullptr,
-                             nullptr, workspace, s, nparts))
-    return rc;
-  if (!fb) return LBM_OK;
-  const SimpleScratch W = simple_scratch();
-  return launch_gate(g_src, g_dst, nx, ny, tau, fb, nparts, at_(workspace, W.pmass),
-                     at_(workspace, W.pflag), at_(workspace, W.pmass2),
-                     at_(workspace, W.ctrl), s);
+  return step_simple("lbm_step_simple", g_src, g_dst, nx, ny, tau, false, 0.0f, params, fb,
+                     workspace, ws_bytes, stream);
+}
+
+extern "C" int lbm_step_simple_channel(const float *g_src, float *g_dst, int nx, int ny,
+                                       float tau, float gx, const float *params,
+                                       const lbm_fallback *fb, void *workspace,
+                                       size_t ws_bytes, void *stream) {
+  return step_simple("lbm_step_simple_channel", g_src, g_dst, nx, ny, tau, true, gx, params, fb,
+                     workspace, ws_bytes, stream);
 }

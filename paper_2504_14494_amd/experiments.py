@@ -302,14 +302,16 @@ def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
 
 
 def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
-                     diffusion_times=4.0, fp64=False):
+                     diffusion_times=4.0, fp64=False, blob=None):
     """Channel flow between resting walls (validation section, "Poiseuille
     Flow", Eq. 5) at several Reynolds numbers Re = u_max ny / nu: each run
     starts at rest and is driven by g = 8 nu u_max / ny^2 for
     `diffusion_times` ny^2 / nu steps (the slowest transient then decays as
     exp(-pi^2 diffusion_times)).  Reports the largest velocity error of the
     x-averaged profile relative to the largest analytic velocity, next to
-    the closed-form bounce-back slip of the method."""
+    the closed-form bounce-back slip of the method.  blob: a zero-round
+    (Fig. 2) parameter blob, run with the per-node corrected collision and
+    its fallback gate instead of BGK (FP32)."""
     rows = []
     for re in re_list:
         nu = u_max * ny / re
@@ -317,12 +319,20 @@ def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
         nu = (tau - 0.5) / 3.0
         g = float(np.float32(8.0 * nu * u_max / ny ** 2))
         steps = int(math.ceil(diffusion_times * ny * ny / nu))
-        lat = lbm.Lattice(nx, ny, dtype=torch.float64 if fp64 else torch.float32)
-        lat.a.zero_()
+        if blob is not None:
+            lat = gnn.GnnLattice(nx, ny, blob, 0)
+            lat.a.zero_()
+            lat.sync_mass()
+        else:
+            lat = lbm.Lattice(nx, ny, dtype=torch.float64 if fp64 else torch.float32)
+            lat.a.zero_()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
-        lat.step_channel(tau, g, steps, graph=True)
+        if blob is not None:
+            lat.step_gnn_channel(tau, g, steps, graph=True)
+        else:
+            lat.step_channel(tau, g, steps, graph=True)
         t1.record()
         torch.cuda.synchronize()
         g32 = lat.a if not fp64 else lbm.lbm_restrict(lat.a, 1, tau, tau, pull=False,
@@ -334,15 +344,20 @@ def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
         rows.append({"re": re, "tau": tau, "g": g, "steps": steps,
                      "max_rel_err": float(np.abs(prof - ua).max() / ua.max()),
                      "slip_rel_closed_form": float(slip / ua.max()),
+                     "fallback_steps": int(lat.n_fallback.item()) if blob is not None else 0,
                      "seconds": t0.elapsed_time(t1) * 1e-3})
-    return {"ny": ny, "nx": nx, "u_max": u_max, "fp64": fp64, "rows": rows}
+    return {"ny": ny, "nx": nx, "u_max": u_max, "fp64": fp64,
+            "collision": "bgk" if blob is None else "fig2-network", "rows": rows}
 
 
 def main(argv=None):
     """Runs one study and prints its report as JSON:
     python -m paper_2504_14494_amd.experiments {fixed-error, resolution,
     stability, poiseuille, long-rollout} [--rounds R].  The corrected-collision
-    studies first train the network (train.train, full configuration)."""
+    studies first train the network (train.train, full configuration); the
+    Poiseuille study runs a network only with --rounds 0 (the per-node
+    network has no neighbours across a wall; message passing has no wall
+    treatment)."""
     import argparse
     import json
     import time
@@ -359,7 +374,8 @@ def main(argv=None):
     t0 = time.perf_counter()
     blob = None
     if args.study in ("fixed-error", "stability", "long-rollout") or (
-            args.study == "resolution" and not args.fp64):
+            args.study == "resolution" and not args.fp64) or (
+            args.study == "poiseuille" and args.rounds == 0 and not args.fp64):
         tr, rep = train.train(train.DataConfig(), steps=2000, batch=32, rounds=args.rounds)
         blob = tr.blob
     if args.study == "fixed-error":
@@ -371,7 +387,9 @@ def main(argv=None):
     elif args.study == "stability":
         out = stability_sweep(blob, rounds=args.rounds)
     elif args.study == "poiseuille":
-        out = poiseuille_study(fp64=args.fp64)
+        out = {"bgk": poiseuille_study(fp64=args.fp64)}
+        if blob is not None:
+            out["fig2_network"] = poiseuille_study(blob=blob)
     else:
         out = long_rollout(blob, rounds=args.rounds, steps=args.steps)
     out["wall_seconds"] = round(time.perf_counter() - t0, 1)

@@ -17,7 +17,8 @@ from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
            "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
-           "GnnMse", "simple_forward", "lbm_step_simple", "gnn_gelu_rate", "collide"]
+           "GnnMse", "simple_forward", "lbm_step_simple", "lbm_step_simple_channel",
+           "gnn_gelu_rate", "collide"]
 
 
 def gnn_param_count(rounds: int = 2) -> int:
@@ -156,22 +157,39 @@ def collide(g_pre: torch.Tensor, tau: torch.Tensor, blob: torch.Tensor, rounds: 
     return gnn_forward(g_pre, tau, blob, rounds, want_z=want_z, saved=saved)
 
 
-def lbm_step_simple(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.Tensor,
-                    fallback: Fallback = None, ws: Workspace = None):
-    """One step with the per-node (Fig. 2) corrected collision fused into the
-    pull step; blob: zero-round layout."""
+def _simple_step_args(src, dst, blob, fallback, ws):
     _need(src, torch.float32, "src")
     _need(dst, torch.float32, "dst")
     if src.dim() != 3 or src.shape[1] != 9 or src.shape != dst.shape:
         raise ValueError("src and dst must both be [ny, 9, nx]")
     _check_blob(blob, 0)
     ny, nx = int(src.shape[0]), int(src.shape[2])
-    L = _lib.load()
-    buf = (ws or _ws).get(L.lbm_workspace_bytes(_lib.LBM_WS_SIMPLE, 1, nx, ny, 0))
+    buf = (ws or _ws).get(_lib.load().lbm_workspace_bytes(_lib.LBM_WS_SIMPLE, 1, nx, ny, 0))
     fb = ctypes.byref(fallback.struct()) if fallback is not None else None
-    rc = L.lbm_step_simple(_ptr(src), _ptr(dst), nx, ny, float(tau), _ptr(blob), fb, _ptr(buf),
-                           buf.numel(), _stream())
+    return nx, ny, fb, buf
+
+
+def lbm_step_simple(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.Tensor,
+                    fallback: Fallback = None, ws: Workspace = None):
+    """One step with the per-node (Fig. 2) corrected collision fused into the
+    pull step; blob: zero-round layout."""
+    nx, ny, fb, buf = _simple_step_args(src, dst, blob, fallback, ws)
+    rc = _lib.load().lbm_step_simple(_ptr(src), _ptr(dst), nx, ny, float(tau), _ptr(blob), fb,
+                                     _ptr(buf), buf.numel(), _stream())
     check(rc, "lbm_step_simple")
+    return dst
+
+
+def lbm_step_simple_channel(src: torch.Tensor, dst: torch.Tensor, tau: float, gx: float,
+                            blob: torch.Tensor, fallback: Fallback = None,
+                            ws: Workspace = None):
+    """lbm_step_simple on the forced channel (bounce-back walls below row 0
+    and above row ny - 1, body force rho * gx along x)."""
+    nx, ny, fb, buf = _simple_step_args(src, dst, blob, fallback, ws)
+    rc = _lib.load().lbm_step_simple_channel(_ptr(src), _ptr(dst), nx, ny, float(tau),
+                                             float(gx), _ptr(blob), fb, _ptr(buf), buf.numel(),
+                                             _stream())
+    check(rc, "lbm_step_simple_channel")
     return dst
 
 
@@ -243,6 +261,28 @@ class GnnLattice(Lattice):
             step(self.a.clone(), torch.empty_like(self.a), tmp)
         return self._run(("gnn", float(tau), bool(gate)), lambda s, d: step(s, d, fb), warm, n,
                          graph)
+
+    def step_gnn_channel(self, tau: float, gx: float, n: int = 1, gate: bool = True,
+                         graph: bool = False):
+        """Corrected steps of the per-node network (rounds == 0) on the
+        forced channel; the fallback is the forced BGK channel step."""
+        if self.rounds != 0:
+            raise ValueError("the channel step runs the per-node network (rounds = 0): "
+                             "message passing has no wall treatment")
+
+        def step(src, dst, fb):
+            lbm_step_simple_channel(src, dst, tau, gx, self.blob, fb, self.ws)
+
+        fb = self.fallback if gate else None
+
+        def warm():
+            tmp = None
+            if gate:
+                tmp = Fallback(0.0, self.fallback.threshold)
+                tmp.mass.copy_(self.fallback.mass)
+            step(self.a.clone(), torch.empty_like(self.a), tmp)
+        return self._run(("gnn_channel", float(tau), float(gx), bool(gate)),
+                         lambda s, d: step(s, d, fb), warm, n, graph)
 
 
 def backward_ws_bytes(batch: int, nx: int, ny: int, rounds: int = 2) -> int:

@@ -85,6 +85,10 @@ def test_every_entry_point_rejects_bad_arguments_before_device_work():
         ("gnn_mse", (a, b, 0, 4, 4, 1.0, c, d, e, 1 << 30, None), EINVAL),
         ("gnn_adam", (a, b, c, d, 16, 1e-3, 0.9, 0.999, 1e-8, 0, None), EINVAL),
         ("lbm_step_simple", (a, b, 4, 4, -1.0, c, None, d, 1 << 30, None), EINVAL),
+        ("lbm_step_simple_channel", (a, b, 4, 4, 0.7, float("nan"), c, None, d, 1 << 30, None),
+         EINVAL),
+        ("lbm_step_simple_channel", (a, a, 4, 4, 0.7, 1e-4, c, None, d, 1 << 30, None), EINVAL),
+        ("lbm_step_simple_channel", (a, b, 4, 4, 0.7, 1e-4, c, None, d, 16, None), EWORKSPACE),
         ("simple_forward", (a, a, 1, 4, 4, b, c, None, None, 0, d, 1 << 30, None), EINVAL),
         ("simple_forward", (a, b, 1, 4, 4, b, c, None, e, 16, d, 1 << 30, None), EWORKSPACE),
     ]

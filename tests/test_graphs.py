@@ -84,6 +84,29 @@ def test_fallback_inside_a_graph_matches_eager(rounds):
     assert torch.equal(e.fallback.mass, g.fallback.mass)
 
 
+@pytest.mark.parametrize("bad_head", [False, True])
+def test_corrected_channel_step_graph_replays_equal_eager_steps(bad_head):
+    """The per-node network on the forced channel, with the gate; a bad head
+    makes every step fall back to the forced BGK channel step."""
+    blob = inputs.gnn_blob(6, 0, s_delta=1.0 if bad_head else 1e-4)
+    if bad_head:
+        o, _ = inputs.blob_offsets(0)["bh"]
+        blob[o + 1:o + 3] = np.float32([50, -50])
+    blob = torch.as_tensor(blob, device="cuda")
+
+    def make():
+        lat = gnn.GnnLattice(7, 20, blob, 0)
+        lat.a.zero_()
+        lat.sync_mass()
+        return lat
+    e, g = _twins(make)
+    _check_replays(e, g, lambda lat, n, gr: lat.step_gnn_channel(0.75, 2e-4, n, graph=gr),
+                   rounds=2)
+    assert torch.equal(e.fallback.mass, g.fallback.mass)
+    assert torch.equal(e.n_fallback, g.n_fallback)
+    assert (int(g.n_fallback.item()) == g.steps) == bad_head
+
+
 def test_graph_keeps_its_buffers_when_the_workspace_grows():
     """A captured graph holds the workspace it was captured with; growing the
     lattice's workspace afterwards (a new buffer) leaves replays valid."""
