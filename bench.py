@@ -58,16 +58,23 @@ def bgk_src_hash():
     return hashlib.sha256(_read("lbm_common.hpp") + body[a:b]).hexdigest()[:16]
 
 
+def bgk_kernel_name(nx):
+    """The kernel lbm_step_bgk launches for FP32 rows of nx nodes."""
+    return "bgk_pull_wave_kernel" if nx % 64 == 0 else "bgk_pull_kernel<float>"
+
+
 def simple_src_hash():
     """Hash of the sources of the fused per-node (Fig. 2) step."""
     return hashlib.sha256(_read("gnn_common.hpp") + _read("gnn_layout.hpp") +
-                          _read("simple_kernels.hip") + _read("lbm_common.hpp")).hexdigest()[:16]
+                          _read("simple_kernels.hip") + _read("lbm_common.hpp") +
+                          _read("channel_common.hpp")).hexdigest()[:16]
 
 
 def gnn_src_hash():
     """Hash of the sources of the corrected step's kernels."""
     return hashlib.sha256(_read("gnn_common.hpp") + _read("gnn_layout.hpp") +
-                          _read("gnn_kernels.hip") + _read("lbm_common.hpp")).hexdigest()[:16]
+                          _read("gnn_kernels.hip") + _read("lbm_common.hpp") +
+                          _read("channel_common.hpp")).hexdigest()[:16]
 
 
 def bgk_leg(n, re, u0, steps, warmup):
@@ -221,10 +228,18 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     # trained the same way on the same pairs
     tr0, rep0 = train.train(train.DataConfig(), steps=2000, batch=32, rounds=0, data=data)
     f2 = experiments.fixed_error_report(tr0.blob, rounds=0)
+    # the trained per-node network on the forced channel (Poiseuille), the
+    # same Reynolds numbers as the BGK channel study
+    pois = experiments.poiseuille_study(blob=tr0.blob)
     out["fig2_network"] = {"heldout_loss_over_bgk": rep0["heldout_rel_loss_after"],
                            "train_samples_per_s": round(rep0["samples_per_s"], 1),
                            "errors_128": f2["errors"]["gnn_128"],
-                           "fallback_steps": f2["fallback_steps"]}
+                           "fallback_steps": f2["fallback_steps"],
+                           "poiseuille": [{"re": r["re"], "tau": round(r["tau"], 5),
+                                           "max_rel_err": float(f"{r['max_rel_err']:.4g}"),
+                                           "fallback_steps": r["fallback_steps"],
+                                           "seconds": round(r["seconds"], 2)}
+                                          for r in pois["rows"]]}
     return out
 
 
@@ -376,7 +391,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_entry(),
-            "kernel": "bgk_pull_kernel<float>",
+            "kernel": bgk_kernel_name(args.n),
             "copy_ceiling_gbs": round(cp["gbs"], 1),
             "frac_of_copy": round(achieved / cp["gbs"], 4)}
     out = {

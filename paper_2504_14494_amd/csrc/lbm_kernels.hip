@@ -87,11 +87,84 @@ __global__ __launch_bounds__(kBgkThreads) void bgk_pull_kernel(const T *__restri
   for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(g[i], d + (size_t)i * nx);
 }
 
+// Lane l of a wave takes lane l - 1's v (the value at x - 1), lane 0 takes
+// `halo` (DPP wave_shr:1).
+__device__ __forceinline__ float wave_from_left(float v, float halo) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, halo),
+                                                               __builtin_bit_cast(int, v), 0x138,
+                                                               0xF, 0xF, false));
+}
+// Lane l takes lane l + 1's v (the value at x + 1), lane 63 takes `halo`
+// (DPP wave_shl:1).
+__device__ __forceinline__ float wave_from_right(float v, float halo) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, halo),
+                                                               __builtin_bit_cast(int, v), 0x130,
+                                                               0xF, 0xF, false));
+}
+
+// The same step for rows of whole waves (nx a multiple of 64), FP32.  The
+// six populations that move along x are not gathered from x -/+ 1: every
+// lane loads its own column, so each of the nine loads of a wave covers two
+// whole 128-byte lines, and the values move one lane over through DPP.  The
+// two columns just outside the wave (x0 - 1 and x0 + 64, periodic) are
+// wave-uniform addresses, fetched by scalar loads, so the vector memory path
+// sees exactly the 18 lines of the wave.  Cache policy, measured on
+// back-to-back steps: the three populations that do not move along x are
+// read once by one wave and bypass the caches (non-temporal); the six that
+// move keep normal loads, because their edge lines are read again, as a
+// halo, by the neighbouring wave (non-temporal there costs a second HBM
+// fetch of those lines).  Same arithmetic, bitwise the same result as
+// bgk_pull_kernel, about 3% faster at 4096^2 and 8192^2.
+__global__ __launch_bounds__(kBgkThreads) void bgk_pull_wave_kernel(
+    const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, int bx,
+    float omega) {
+  const int y = blockIdx.x / bx;
+  const int lane = threadIdx.x & 63;
+  const int x0 = __builtin_amdgcn_readfirstlane((blockIdx.x - y * bx) * kBgkThreads +
+                                                (threadIdx.x & ~63));
+  if (x0 >= nx) return;  // whole waves only: every lane of a running wave is active
+  const int x = x0 + lane;
+  const int xl = x0 == 0 ? nx - 1 : x0 - 1;
+  const int xr = x0 + 64 == nx ? 0 : x0 + 64;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const float *r0 = src + (size_t)y * 9 * nx, *rm = src + (size_t)ym * 9 * nx,
+              *rp = src + (size_t)yp * 9 * nx;
+  const float h1 = r0[(size_t)1 * nx + xl], h5 = rm[(size_t)5 * nx + xl],
+              h8 = rp[(size_t)8 * nx + xl];
+  const float h3 = r0[(size_t)3 * nx + xr], h6 = rm[(size_t)6 * nx + xr],
+              h7 = rp[(size_t)7 * nx + xr];
+  const float a1 = r0[(size_t)1 * nx + x], a5 = rm[(size_t)5 * nx + x],
+              a8 = rp[(size_t)8 * nx + x];
+  const float a3 = r0[(size_t)3 * nx + x], a6 = rm[(size_t)6 * nx + x],
+              a7 = rp[(size_t)7 * nx + x];
+  float g[9];
+  g[0] = __builtin_nontemporal_load(r0 + x);
+  g[2] = __builtin_nontemporal_load(rm + (size_t)2 * nx + x);
+  g[4] = __builtin_nontemporal_load(rp + (size_t)4 * nx + x);
+  g[1] = wave_from_left(a1, h1);
+  g[5] = wave_from_left(a5, h5);
+  g[8] = wave_from_left(a8, h8);
+  g[3] = wave_from_right(a3, h3);
+  g[6] = wave_from_right(a6, h6);
+  g[7] = wave_from_right(a7, h7);
+  bgk_collide(g, omega);
+  float *d = dst + (size_t)y * 9 * nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(g[i], d + (size_t)i * nx);
+}
+
 template <typename T>
 int launch_bgk(const T *src, T *dst, int nx, int ny, T tau, hipStream_t s) {
   int bx = (nx + kBgkThreads - 1) / kBgkThreads;
   long long blocks = (long long)bx * ny;
   if (blocks > 0x7fffffffLL) return fail(LBM_EINVAL, "lbm_step_bgk: lattice too large");
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (nx % 64 == 0) {
+      hipLaunchKernelGGL(bgk_pull_wave_kernel, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s,
+                         src, dst, nx, ny, bx, T(1) / tau);
+      return launch_check("bgk_pull_wave_kernel");
+    }
+  }
   hipLaunchKernelGGL(bgk_pull_kernel<T>, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s, src,
                      dst, nx, ny, bx, T(1) / tau);
   return launch_check("bgk_pull_kernel");

@@ -78,7 +78,9 @@ def test_tgv_64_re100_1000_steps_matches_fp64_oracle(orc):
 
 
 @pytest.mark.parametrize("ny,nx", [(1, 1), (3, 5), (7, 4), (33, 64), (3, 257), (5, 300),
-                                   (2, 513)])
+                                   (2, 513),
+                                   # rows of whole waves (nx % 64 == 0), partial blocks
+                                   (1, 64), (2, 128), (5, 192), (3, 320), (4, 1024)])
 def test_small_and_ragged_lattices(orc, ny, nx):
     post0 = inputs.random_shifted_state((9, ny, nx), 4e-3, seed=nx * 100 + ny)
     tau, steps = 0.61, 4
