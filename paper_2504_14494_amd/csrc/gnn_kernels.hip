@@ -314,24 +314,54 @@ __device__ __forceinline__ void gnn_collide(float (&g)[9], const float (&z)[NOUT
   }
 }
 
-// One round over 16 x 16 receiver tiles taken grid-stride.  The workgroup
-// stages the node states of the tile and its ring (18 x 18 nodes, BF16) in
-// LDS; wave w handles tile rows 4w..4w+3, 16 receivers (one MFMA column
-// block) at a time.  With HEAD the round is the last one: the head, the
-// projection and the corrected collision follow, written to args.dst.
-// Register budget (two waves per SIMD): only the sender weights Wb, used 8
-// times per receiver, stay in VGPRs; Wa, Wn, the head and the biases are read
-// from LDS where they are used.
+// One round over 16 x 16 receiver tiles taken grid-stride, one 8-wave
+// workgroup per CU.  The node states of a tile and its ring (18 x 18 nodes,
+// BF16) sit in LDS; wave w handles tile rows 2w and 2w + 1, 16 receivers (one
+// MFMA column block) at a time.  Two halo buffers alternate: while the waves
+// work on one tile, direct-to-LDS loads (global_load_lds_dwordx4, no
+// registers) fill the other with the next tile's halo, so fetching the node
+// states overlaps the arithmetic instead of stalling it.  With HEAD the round
+// is the last one: the head, the projection and the corrected collision
+// follow, written to args.dst.  Register budget (two waves per SIMD): only
+// the sender weights Wb, used 8 times per receiver, stay in VGPRs; Wa, Wn,
+// the head and the biases are read from LDS where they are used.
+constexpr int kRoundThreads = 512;
+constexpr int kRoundWaves = kRoundThreads / 64;
+constexpr int kRowsPerWave = TILE / kRoundWaves;
+// A halo buffer is a run of 16-byte slots, node ln's chunk c at slot 9 ln + c
+// (slot 9 ln + 8 is the padding of kNodeBytes); one direct-to-LDS load fills
+// 64 consecutive slots.
+constexpr int kStageLoads = (HNODES * 9 + 63) / 64;
+constexpr int kHaloBytes = kStageLoads * 64 * 16;
+static_assert(kNodeBytes == 9 * 16, "a node is nine 16-byte slots");
+static_assert(kRowsPerWave * kRoundWaves == TILE, "tile rows split over the waves");
+// s_waitcnt with vmcnt(0) and the other counters left at their maximum: waits
+// for this wave's vector memory operations only (the stores counted too).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Workgroup barrier that makes this wave's LDS writes visible (lgkmcnt(0))
+// but does not wait for its global stores.  __syncthreads() cannot be used
+// inside the tile loop: with direct-to-LDS loads in the kernel its release
+// fence waits for every vector memory operation, the fresh stores of the
+// tile included.  The loads into LDS are waited for explicitly
+// (kWaitVmcnt0) before the barrier that publishes them; the memory clobber
+// keeps the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <bool HEAD, bool PULL, bool SAVE>
-__global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
+__global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
     const uint16_t *__restrict__ hin, uint16_t *__restrict__ hout,
     uint16_t *__restrict__ save_agg, int batch, int nx, int ny, int round,
     const uint8_t *__restrict__ pack, FragLayout F, HeadArgs args) {
-  __shared__ __attribute__((aligned(16))) uint8_t hs[HNODES * kNodeBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t hs_a[kHaloBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t hs_b[kHaloBytes];
   __shared__ u32x4 wa_s[8 * 64];
   __shared__ u32x4 wn_s[16 * 64];
-  // head outputs of the wave's 64 nodes; reused for the final reduction
-  __shared__ __attribute__((aligned(16))) float zb[HEAD ? kWaves * 64 * NOUT : 1];
+  // head outputs of the tile's 256 nodes; reused for the final reduction
+  __shared__ __attribute__((aligned(16))) float zb[HEAD ? TILE * TILE * NOUT : 1];
+  static_assert(!HEAD || TILE * TILE * NOUT >= 3 * kRoundThreads, "reduction fits in zb");
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
@@ -339,9 +369,9 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
   const f32x4 *bias = (const f32x4 *)(pack + F.bias_off);
   const float *cst = (const float *)(pack + F.const_off);
 
-  for (int k = threadIdx.x; k < 8 * 64; k += kThreads)
+  for (int k = threadIdx.x; k < 8 * 64; k += kRoundThreads)
     wa_s[k] = frags[(size_t)F.WA[round] * 64 + k];
-  for (int k = threadIdx.x; k < 16 * 64; k += kThreads)
+  for (int k = threadIdx.x; k < 16 * 64; k += kRoundThreads)
     wn_s[k] = frags[(size_t)F.WN[round] * 64 + k];
   u32x4 wb[4][2];
   uint32_t wc[4];  // only lanes q == 0 hold a non-zero (first) dword
@@ -369,49 +399,60 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
   double mass_acc = 0.0;
   unsigned flag_acc = 0;
 
-  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  struct TileAt {
+    int x0, y0, b;
+    size_t lat_nodes;
+  };
+  auto tile_at = [&](long long tile) {
+    TileAt T;
     const int tx = (int)(tile % txn);
     const long long rest = tile / txn;
-    const int ty = (int)(rest % tyn), b = (int)(rest / tyn);
-    const int x0 = tx * TILE, y0 = ty * TILE;
-    const size_t lat_nodes = (size_t)b * ny * nx;
+    const int ty = (int)(rest % tyn);
+    T.b = (int)(rest / tyn);
+    T.x0 = tx * TILE;
+    T.y0 = ty * TILE;
+    T.lat_nodes = (size_t)T.b * ny * nx;
+    return T;
+  };
 
-    __syncthreads();  // weights staged / previous tile no longer read
-    {
-      // chunk k = threadIdx.x + 256 j: node ln = k / 8 of the halo, 16-byte
-      // chunk c = k % 8.  ln advances by 32 = 18 + 14 per j, so the halo
-      // coordinates step without a division, and the periodic wrap of a
-      // coordinate that is at most one period off is a compare.
-      const int c = threadIdx.x & 7;
-      int ln = threadIdx.x >> 3;
-      int hy = ln / HALO, hx = ln - hy * HALO;
-      for (; ln < HNODES; ln += kThreads / 8) {
-        int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
-        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-        if (gx >= nx) gx = wrapi(gx, nx);  // lattices narrower than the halo
-        if (gy >= ny) gy = wrapi(gy, ny);
-        const u32x4 *srcp = (const u32x4 *)(hin + (lat_nodes + (size_t)gy * nx + gx) * HID);
-        *(u32x4 *)(hs + ln * kNodeBytes + c * 16) = srcp[c];
-        hx += (kThreads / 8) % HALO;
-        hy += (kThreads / 8) / HALO;
-        if (hx >= HALO) {
-          hx -= HALO;
-          ++hy;
-        }
-      }
+  // Issues the direct-to-LDS loads of a tile's halo into `buf`: load k of
+  // this wave fills slots 64 k .. 64 k + 63, lane l slot 64 k + l.  Padding
+  // slots take a copy of chunk 7, slots past the last node a copy of the last
+  // node: every address is a valid node state, every slot inside `buf`.
+  auto stage = [&](long long tile, uint8_t *buf) {
+    const TileAt T = tile_at(tile);
+    for (int k = wave; k < kStageLoads; k += kRoundWaves) {
+      const int slot = 64 * k + lane;
+      int ln = slot / 9;
+      int c = slot - 9 * ln;
+      if (ln >= HNODES) ln = HNODES - 1;
+      if (c == 8) c = 7;
+      const int hy = ln / HALO, hx = ln - hy * HALO;
+      int gx = T.x0 - 1 + hx, gy = T.y0 - 1 + hy;
+      gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+      gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+      if (gx >= nx) gx = wrapi(gx, nx);  // lattices narrower than the halo
+      if (gy >= ny) gy = wrapi(gy, ny);
+      const uint16_t *src = hin + (T.lat_nodes + (size_t)gy * nx + gx) * HID + c * 8;
+      __builtin_amdgcn_global_load_lds(
+          (const void *)src, (__attribute__((address_space(3))) void *)(buf + k * 1024), 16, 0,
+          0);
     }
-    __syncthreads();
+  };
 
+  // The receivers of one tile from the halo in `hs`.
+  auto compute = [&](const TileAt &T, const uint8_t *hs) {
+    const int x0 = T.x0, y0 = T.y0, b = T.b;
+    const size_t lat_nodes = T.lat_nodes;
 #pragma unroll 1
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kRowsPerWave; ++r) {
       // An offset the compiler cannot see through, so that the LDS weight
       // reads below stay inside the loop instead of being hoisted into
       // registers (which would halve the waves per SIMD).
       int wo = lane;
       asm volatile("" : "+v"(wo));
       const u32x4 *wa = wa_s + wo, *wn = wn_s + wo;
-      const int tyl = wave * 4 + r;
+      const int tyl = wave * kRowsPerWave + r;
       const int x = x0 + n, y = y0 + tyl;
       // chunk q of the lower-left neighbour (dx = dy = -1) of this receiver;
       // every neighbour's chunk is at a constant offset from it
@@ -470,6 +511,14 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
         p[t] = gelu4(p[t]);
       }
       u32x4 hb[2] = {frag_from_acc(p[0], p[1]), frag_from_acc(p[2], p[3])};
+      // This wave's loads of the next tile's halo, issued at the start of the
+      // tile, are complete before its first store of the tile: the barrier
+      // that starts the next tile then needs no wait on memory, and the
+      // stores drain while the next tile is computed.  (The wait is in every
+      // row: before the second row it also covers the first row's stores,
+      // issued half a tile earlier; unconditional, it also tells the
+      // compiler that no load into a halo buffer is pending after a tile.)
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       if (x < nx && y < ny) {
         const size_t node = lat_nodes + (size_t)y * nx + x;
         if (hout) {
@@ -490,19 +539,20 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           int k = 4 * q + e;
-          if (k < NOUT) zb[(wave * 64 + r * 16 + n) * NOUT + k] = zz[e];
+          if (k < NOUT) zb[(tyl * TILE + n) * NOUT + k] = zz[e];
         }
       }
     }
 
     if constexpr (HEAD) {
-      __syncthreads();
-      // lane -> node (n, row r = lane / 16) of this wave's four tile rows
-      const int x = x0 + n, y = y0 + wave * 4 + q;
-      if (x < nx && y < ny) {
+      lds_barrier();
+      // lanes 0..31: node (n, row q) of this wave's two tile rows
+      const int tyl = wave * kRowsPerWave + q;
+      const int x = x0 + n, y = y0 + tyl;
+      if (q < kRowsPerWave && x < nx && y < ny) {
         float z[NOUT];
 #pragma unroll
-        for (int k = 0; k < NOUT; ++k) z[k] = zb[(wave * 64 + lane) * NOUT + k];
+        for (int k = 0; k < NOUT; ++k) z[k] = zb[(tyl * TILE + n) * NOUT + k];
         const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
         const size_t lat_off = (size_t)b * ny * 9 * nx;
         float gp[9];
@@ -527,16 +577,40 @@ __global__ __launch_bounds__(kThreads, 2) void gnn_round_kernel(
           for (int k = 0; k < NOUT; ++k) args.save_z[node * 12 + k] = z[k];
       }
     }
+  };
+
+  // Tile i of this workgroup works from hs_a when i is even and from hs_b
+  // when odd; each half of the loop names its buffers directly, so the
+  // compiler can tell the LDS reads of one buffer from the loads in flight
+  // into the other.  Every wave has waited for its own loads into the current
+  // buffer (below for the first tile, inside the previous tile's work for the
+  // others); the barrier at the top of each half makes all of them visible
+  // and tells that the other buffer is no longer read.
+  long long tile = blockIdx.x;
+  if (tile < ntiles) stage(tile, hs_a);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  while (tile < ntiles) {
+    lds_barrier();
+    long long next = tile + gridDim.x;
+    if (next < ntiles) stage(next, hs_b);
+    compute(tile_at(tile), hs_a);
+    tile = next;
+    if (tile >= ntiles) break;
+    lds_barrier();
+    next = tile + gridDim.x;
+    if (next < ntiles) stage(next, hs_a);
+    compute(tile_at(tile), hs_b);
+    tile = next;
   }
 
   if constexpr (HEAD) {
     __syncthreads();  // last tile's head outputs consumed
     double *red_m = (double *)zb;
-    unsigned *red_f = (unsigned *)(zb + 2 * kThreads);
+    unsigned *red_f = (unsigned *)(zb + 2 * kRoundThreads);
     red_m[threadIdx.x] = mass_acc;
     red_f[threadIdx.x] = flag_acc;
     __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
+    for (int s = kRoundThreads / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
         red_m[threadIdx.x] += red_m[threadIdx.x + s];
         red_f[threadIdx.x] |= red_f[threadIdx.x + s];
@@ -732,7 +806,7 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
   if (int rc = launch_check("gnn_encode_kernel")) return rc;
 
   long long ntiles = (long long)batch * ((nx + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE);
-  long long cap = (long long)cus * 2;
+  long long cap = (long long)cus;
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   int rb = (int)(ntiles < cap ? ntiles : cap);
   nparts = rb;
@@ -754,19 +828,19 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
                          : nullptr;
     if (!head) {
       if (save)
-        hipLaunchKernelGGL((gnn_round_kernel<false, false, true>), dim3(rb), dim3(kThreads), 0,
+        hipLaunchKernelGGL((gnn_round_kernel<false, false, true>), dim3(rb), dim3(kRoundThreads), 0,
                            s, hin, hout, sag, batch, nx, ny, r, pack, F, none);
       else
-        hipLaunchKernelGGL((gnn_round_kernel<false, false, false>), dim3(rb), dim3(kThreads), 0,
+        hipLaunchKernelGGL((gnn_round_kernel<false, false, false>), dim3(rb), dim3(kRoundThreads), 0,
                            s, hin, hout, sag, batch, nx, ny, r, pack, F, none);
     } else if (pull) {
-      hipLaunchKernelGGL((gnn_round_kernel<true, true, false>), dim3(rb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((gnn_round_kernel<true, true, false>), dim3(rb), dim3(kRoundThreads), 0, s,
                          hin, hout, sag, batch, nx, ny, r, pack, F, ha);
     } else if (save) {
-      hipLaunchKernelGGL((gnn_round_kernel<true, false, true>), dim3(rb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((gnn_round_kernel<true, false, true>), dim3(rb), dim3(kRoundThreads), 0, s,
                          hin, hout, sag, batch, nx, ny, r, pack, F, ha);
     } else {
-      hipLaunchKernelGGL((gnn_round_kernel<true, false, false>), dim3(rb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((gnn_round_kernel<true, false, false>), dim3(rb), dim3(kRoundThreads), 0, s,
                          hin, hout, sag, batch, nx, ny, r, pack, F, ha);
     }
     if (int rc = launch_check("gnn_round_kernel")) return rc;
