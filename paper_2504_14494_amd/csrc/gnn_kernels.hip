@@ -261,9 +261,11 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
 
 // ------------------------------------------------- message passing round ---
 
-constexpr int TILE = 16;            // receivers per tile edge
-constexpr int HALO = TILE + 2;      // node states of the tile and its 1-node ring
-constexpr int HNODES = HALO * HALO;
+constexpr int TILE_X = 16;              // receivers per tile row (one MFMA column block)
+constexpr int TILE_Y = 8;               // tile rows
+constexpr int HALO_X = TILE_X + 2;      // node states of the tile and its 1-node ring
+constexpr int HALO_Y = TILE_Y + 2;
+constexpr int HNODES = HALO_X * HALO_Y;
 
 // LDS node stride: 128 B of state + 16 B of padding.  16 lanes reading the
 // same 16-byte chunk of 16 consecutive nodes then touch 16 disjoint groups of
@@ -314,27 +316,45 @@ __device__ __forceinline__ void gnn_collide(float (&g)[9], const float (&z)[NOUT
   }
 }
 
-// One round over 16 x 16 receiver tiles taken grid-stride, one 8-wave
-// workgroup per CU.  The node states of a tile and its ring (18 x 18 nodes,
+// One round over 16 x 8 receiver tiles taken grid-stride, two 4-wave
+// workgroups per CU.  The node states of a tile and its ring (18 x 10 nodes,
 // BF16) sit in LDS; wave w handles tile rows 2w and 2w + 1, 16 receivers (one
 // MFMA column block) at a time.  Two halo buffers alternate: while the waves
 // work on one tile, direct-to-LDS loads (global_load_lds_dwordx4, no
 // registers) fill the other with the next tile's halo, so fetching the node
-// states overlaps the arithmetic instead of stalling it.  With HEAD the round
-// is the last one: the head, the projection and the corrected collision
-// follow, written to args.dst.  Register budget (two waves per SIMD): only
-// the sender weights Wb, used 8 times per receiver, stay in VGPRs; Wa, Wn,
-// the head and the biases are read from LDS where they are used.
-constexpr int kRoundThreads = 512;
+// states overlaps the arithmetic instead of stalling it.  Two buffers and the
+// weights take 76 KB, so two workgroups share a CU and each fills the other's
+// barrier waits.  With HEAD the round is the last one: the head, the
+// projection and the corrected collision follow, written to args.dst; the
+// head outputs pass through the buffer the tile has just been computed from.
+// Register budget (two waves per SIMD): only the sender weights Wb, used 8
+// times per receiver, stay in VGPRs; Wa, Wn, the head and the biases are read
+// from LDS where they are used.
+constexpr int kRoundThreads = 256;
 constexpr int kRoundWaves = kRoundThreads / 64;
-constexpr int kRowsPerWave = TILE / kRoundWaves;
+constexpr int kRowsPerWave = TILE_Y / kRoundWaves;
 // A halo buffer is a run of 16-byte slots, node ln's chunk c at slot 9 ln + c
 // (slot 9 ln + 8 is the padding of kNodeBytes); one direct-to-LDS load fills
 // 64 consecutive slots.
 constexpr int kStageLoads = (HNODES * 9 + 63) / 64;
 constexpr int kHaloBytes = kStageLoads * 64 * 16;
 static_assert(kNodeBytes == 9 * 16, "a node is nine 16-byte slots");
-static_assert(kRowsPerWave * kRoundWaves == TILE, "tile rows split over the waves");
+static_assert(kRowsPerWave * kRoundWaves == TILE_Y, "tile rows split over the waves");
+static_assert(TILE_X * TILE_Y * NOUT * 4 <= kHaloBytes, "head outputs fit in a halo buffer");
+static_assert(3 * kRoundThreads * 4 <= kHaloBytes, "reduction fits in a halo buffer");
+// Divisions of the staging loop by multiply and shift (full-rate 24-bit
+// multiplies): slot / 9 for every slot of a halo buffer and node / HALO_X for
+// every node, checked here over the whole range.
+constexpr int kDiv9Mul = 7282, kDivHaloMul = 3641;
+constexpr bool magic_divisions_exact() {
+  for (int v = 0; v < kStageLoads * 64; ++v)
+    if (((v * kDiv9Mul) >> 16) != v / 9) return false;
+  for (int v = 0; v < HNODES; ++v)
+    if (((v * kDivHaloMul) >> 16) != v / HALO_X) return false;
+  return true;
+}
+static_assert(HALO_X == 18 && magic_divisions_exact(), "staging divisions");
+
 // s_waitcnt with vmcnt(0) and the other counters left at their maximum: waits
 // for this wave's vector memory operations only (the stores counted too).
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -351,7 +371,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <bool HEAD, bool PULL, bool SAVE>
-__global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
+__global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
     const uint16_t *__restrict__ hin, uint16_t *__restrict__ hout,
     uint16_t *__restrict__ save_agg, int batch, int nx, int ny, int round,
     const uint8_t *__restrict__ pack, FragLayout F, HeadArgs args) {
@@ -359,9 +379,6 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
   __shared__ __attribute__((aligned(16))) uint8_t hs_b[kHaloBytes];
   __shared__ u32x4 wa_s[8 * 64];
   __shared__ u32x4 wn_s[16 * 64];
-  // head outputs of the tile's 256 nodes; reused for the final reduction
-  __shared__ __attribute__((aligned(16))) float zb[HEAD ? TILE * TILE * NOUT : 1];
-  static_assert(!HEAD || TILE * TILE * NOUT >= 3 * kRoundThreads, "reduction fits in zb");
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
@@ -394,7 +411,7 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
     sdelta = cst[C_SDELTA];
   }
 
-  const int txn = (nx + TILE - 1) / TILE, tyn = (ny + TILE - 1) / TILE;
+  const int txn = (nx + TILE_X - 1) / TILE_X, tyn = (ny + TILE_Y - 1) / TILE_Y;
   const long long ntiles = (long long)batch * txn * tyn;
   double mass_acc = 0.0;
   unsigned flag_acc = 0;
@@ -409,8 +426,8 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
     const long long rest = tile / txn;
     const int ty = (int)(rest % tyn);
     T.b = (int)(rest / tyn);
-    T.x0 = tx * TILE;
-    T.y0 = ty * TILE;
+    T.x0 = tx * TILE_X;
+    T.y0 = ty * TILE_Y;
     T.lat_nodes = (size_t)T.b * ny * nx;
     return T;
   };
@@ -421,13 +438,38 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
   // node: every address is a valid node state, every slot inside `buf`.
   auto stage = [&](long long tile, uint8_t *buf) {
     const TileAt T = tile_at(tile);
+    // Interior tiles (the halo wraps nowhere): node (hx, hy) of the halo is
+    // (hy * nx + hx) nodes past the halo's first node, a per-lane offset
+    // computed with 24-bit multiplies.  nx <= 2^20 keeps it in 32 bits.
+    if (T.x0 >= 1 && T.x0 + HALO_X - 1 <= nx && T.y0 >= 1 && T.y0 + HALO_Y - 1 <= ny &&
+        nx <= (1 << 20)) {
+      const uint8_t *base =
+          (const uint8_t *)(hin + (T.lat_nodes + (size_t)(T.y0 - 1) * nx + (T.x0 - 1)) * HID);
+      for (int k = wave; k < kStageLoads; k += kRoundWaves) {
+        const unsigned slot = 64 * k + lane;
+        unsigned ln = __umul24(slot, kDiv9Mul) >> 16;
+        unsigned c = slot - 9 * ln;
+        if (ln >= (unsigned)HNODES) {
+          ln = HNODES - 1;
+          c = 7;
+        }
+        c = c < 7 ? c : 7;
+        const unsigned hy = __umul24(ln, kDivHaloMul) >> 16;
+        const unsigned hx = ln - HALO_X * hy;
+        const unsigned off = (__umul24(hy, (unsigned)nx) + hx) * 128u + c * 16u;
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(base + off),
+            (__attribute__((address_space(3))) void *)(buf + k * 1024), 16, 0, 0);
+      }
+      return;
+    }
     for (int k = wave; k < kStageLoads; k += kRoundWaves) {
       const int slot = 64 * k + lane;
       int ln = slot / 9;
       int c = slot - 9 * ln;
       if (ln >= HNODES) ln = HNODES - 1;
       if (c == 8) c = 7;
-      const int hy = ln / HALO, hx = ln - hy * HALO;
+      const int hy = ln / HALO_X, hx = ln - hy * HALO_X;
       int gx = T.x0 - 1 + hx, gy = T.y0 - 1 + hy;
       gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
       gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
@@ -440,10 +482,12 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
     }
   };
 
-  // The receivers of one tile from the halo in `hs`.
-  auto compute = [&](const TileAt &T, const uint8_t *hs) {
+  // The receivers of one tile from the halo in `hs`; with HEAD the head
+  // outputs then pass through `hs` itself (float zb[TILE_X * TILE_Y][NOUT]).
+  auto compute = [&](const TileAt &T, uint8_t *hs) {
     const int x0 = T.x0, y0 = T.y0, b = T.b;
     const size_t lat_nodes = T.lat_nodes;
+    f32x4 zr[kRowsPerWave];
 #pragma unroll 1
     for (int r = 0; r < kRowsPerWave; ++r) {
       // An offset the compiler cannot see through, so that the LDS weight
@@ -456,9 +500,9 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
       const int x = x0 + n, y = y0 + tyl;
       // chunk q of the lower-left neighbour (dx = dy = -1) of this receiver;
       // every neighbour's chunk is at a constant offset from it
-      const uint8_t *nb = hs + (tyl * HALO + n) * kNodeBytes + q * 16;
+      const uint8_t *nb = hs + (tyl * HALO_X + n) * kNodeBytes + q * 16;
       auto frag_at = [&](int dx, int dy, int s) {
-        return *(const u32x4 *)(nb + ((dy + 1) * HALO + dx + 1) * kNodeBytes + s * 64);
+        return *(const u32x4 *)(nb + ((dy + 1) * HALO_X + dx + 1) * kNodeBytes + s * 64);
       };
       u32x4 hn[2] = {frag_at(0, 0, 0), frag_at(0, 0, 1)};
       f32x4 an[4];
@@ -534,17 +578,24 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
       }
       if constexpr (HEAD) {
         f32x4 z = mfma(wh[0], hb[0], bh);
-        z = mfma(wh[1], hb[1], z);
-        float zz[4] = {z.x, z.y, z.z, z.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int k = 4 * q + e;
-          if (k < NOUT) zb[(tyl * TILE + n) * NOUT + k] = zz[e];
-        }
+        zr[r] = mfma(wh[1], hb[1], z);
       }
     }
 
     if constexpr (HEAD) {
+      // every wave is done reading the halo: its buffer takes the head outputs
+      float *zb = (float *)hs;
+      lds_barrier();
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) {
+        const int tyl = wave * kRowsPerWave + r;
+        const float zz[4] = {zr[r].x, zr[r].y, zr[r].z, zr[r].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int k = 4 * q + e;
+          if (k < NOUT) zb[(tyl * TILE_X + n) * NOUT + k] = zz[e];
+        }
+      }
       lds_barrier();
       // lanes 0..31: node (n, row q) of this wave's two tile rows
       const int tyl = wave * kRowsPerWave + q;
@@ -552,7 +603,7 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
       if (q < kRowsPerWave && x < nx && y < ny) {
         float z[NOUT];
 #pragma unroll
-        for (int k = 0; k < NOUT; ++k) z[k] = zb[(tyl * TILE + n) * NOUT + k];
+        for (int k = 0; k < NOUT; ++k) z[k] = zb[(tyl * TILE_X + n) * NOUT + k];
         const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
         const size_t lat_off = (size_t)b * ny * 9 * nx;
         float gp[9];
@@ -605,8 +656,8 @@ __global__ __launch_bounds__(kRoundThreads) void gnn_round_kernel(
 
   if constexpr (HEAD) {
     __syncthreads();  // last tile's head outputs consumed
-    double *red_m = (double *)zb;
-    unsigned *red_f = (unsigned *)(zb + 2 * kRoundThreads);
+    double *red_m = (double *)hs_a;
+    unsigned *red_f = (unsigned *)(hs_a + 8 * kRoundThreads);
     red_m[threadIdx.x] = mass_acc;
     red_f[threadIdx.x] = flag_acc;
     __syncthreads();
@@ -805,8 +856,9 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
   }
   if (int rc = launch_check("gnn_encode_kernel")) return rc;
 
-  long long ntiles = (long long)batch * ((nx + TILE - 1) / TILE) * ((ny + TILE - 1) / TILE);
-  long long cap = (long long)cus;
+  long long ntiles =
+      (long long)batch * ((nx + TILE_X - 1) / TILE_X) * ((ny + TILE_Y - 1) / TILE_Y);
+  long long cap = (long long)cus * 2;
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   int rb = (int)(ntiles < cap ? ntiles : cap);
   nparts = rb;
