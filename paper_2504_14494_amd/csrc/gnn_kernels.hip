@@ -290,7 +290,9 @@ struct HeadArgs {
   unsigned *pflag;        // [gridDim.x] 1 if a population came out negative / non-finite
 };
 
-// Corrected collision of one node (Eq. 3 with the projected correction).
+// Corrected collision of one node (Eq. 3 with the projected correction),
+// populations I0 .. I1 - 1 (the moments and the projection use all nine).
+template <int I0 = 0, int I1 = 9>
 __device__ __forceinline__ void gnn_collide(float (&g)[9], const float (&z)[NOUT], float tau,
                                            float sdelta) {
   float drho, rho, u, v, uu;
@@ -309,7 +311,7 @@ __device__ __forceinline__ void gnn_collide(float (&g)[9], const float (&z)[NOUT
   mx *= (1.0f / 6.0f);
   my *= (1.0f / 6.0f);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
+  for (int i = I0; i < I1; ++i) {
     float relaxed = g[i] + omega * (lbm::geq_shifted<float>(i, drho, rho, u, v, uu) - g[i]);
     float df = z[1 + i] - m0 - float(cx(i)) * mx - float(cy(i)) * my;
     g[i] = relaxed + sdelta * df;
@@ -597,35 +599,48 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
         }
       }
       lds_barrier();
-      // lanes 0..31: node (n, row q) of this wave's two tile rows
-      const int tyl = wave * kRowsPerWave + q;
-      const int x = x0 + n, y = y0 + tyl;
-      if (q < kRowsPerWave && x < nx && y < ny) {
+      // The collision of the tile's 128 nodes: waves 2j and 2j + 1 take nodes
+      // 64 j .. 64 j + 63, one per lane, and split the nine populations
+      // between them (0-4 and 5-8), so every lane of every wave works.
+      const int nl = (wave >> 1) * 64 + lane;
+      const int tyl = nl / TILE_X, nxl = nl - tyl * TILE_X;
+      const int x = x0 + nxl, y = y0 + tyl;
+      const bool lo = (wave & 1) == 0;
+      static_assert(TILE_X * TILE_Y == 2 * 64 && kRoundWaves == 4, "epilogue split");
+      if (x < nx && y < ny) {
         float z[NOUT];
 #pragma unroll
-        for (int k = 0; k < NOUT; ++k) z[k] = zb[(tyl * TILE_X + n) * NOUT + k];
+        for (int k = 0; k < NOUT; ++k) z[k] = zb[nl * NOUT + k];
         const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
         const size_t lat_off = (size_t)b * ny * 9 * nx;
         float gp[9];
         node_pops<PULL>(args.src + lat_off, nx, ny, x, y, gp);
-        gnn_collide(gp, z, tau, sdelta);
         float *d = args.dst + lat_off + (size_t)y * 9 * nx + x;
         double msum = 0.0;
         unsigned bad = 0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
+        auto finish = [&](int i) {
           __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
           float f = gp[i] + lbm::wgt<float>(i);
           bad |= (f >= 0.0f && f < INFINITY) ? 0u : 1u;
           msum += (double)gp[i];
+        };
+        if (lo) {
+          gnn_collide<0, 5>(gp, z, tau, sdelta);
+#pragma unroll
+          for (int i = 0; i < 5; ++i) finish(i);
+        } else {
+          gnn_collide<5, 9>(gp, z, tau, sdelta);
+#pragma unroll
+          for (int i = 5; i < 9; ++i) finish(i);
         }
         mass_acc += msum;
         flag_acc |= bad;
         const size_t node = lat_nodes + (size_t)y * nx + x;
-        if (args.head_out)
+        if (lo && args.head_out)
           for (int k = 0; k < NOUT; ++k) args.head_out[node * NOUT + k] = z[k];
         if constexpr (SAVE)
-          for (int k = 0; k < NOUT; ++k) args.save_z[node * 12 + k] = z[k];
+          if (lo)
+            for (int k = 0; k < NOUT; ++k) args.save_z[node * 12 + k] = z[k];
       }
     }
   };
