@@ -49,20 +49,32 @@ __device__ __forceinline__ u32x4 relu_frag(f32x4 lo, f32x4 hi) {
   return u32x4{relu_bf16x2(r.x), relu_bf16x2(r.y), relu_bf16x2(r.z), relu_bf16x2(r.w)};
 }
 
-// Eq. 3 with the projected correction at one node.  The sigmoid and the
-// relaxation rate use the hardware exp2 and reciprocal (about 1 ulp each);
-// z0 = 0 still gives tau_adj = 1 exactly (2^0 = 1, 1/2 = 0.5).  FORCED: under
-// the channel's body force rho * gx, f^eq is taken at Guo's velocity and
-// Guo's source is added at the effective rate omega = 1 / (tau tau_adj).
+// Density deviation, density and velocity of a node, as lbm::node_moments
+// (same sums, same order) but with the hardware reciprocal of rho (about
+// 1 ulp) instead of an IEEE division.
+__device__ __forceinline__ void moments(const float (&g)[9], float &drho, float &rho, float &u,
+                                        float &v) {
+  drho = ((g[0] + (g[1] + g[3])) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
+  const float jx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
+  const float jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
+  rho = 1.0f + drho;
+  const float inv = __builtin_amdgcn_rcpf(rho);
+  u = jx * inv;
+  v = jy * inv;
+}
+
+// Eq. 3 with the projected correction at one node, given its moments (the
+// velocity without the force).  The sigmoid and the relaxation rate use the
+// hardware exp2 and reciprocal (about 1 ulp each); z0 = 0 still gives
+// tau_adj = 1 exactly (2^0 = 1, 1/2 = 0.5).  FORCED: under the channel's body
+// force rho * gx, f^eq is taken at Guo's velocity and Guo's source is added at
+// the effective rate omega = 1 / (tau tau_adj).
 template <bool FORCED>
 __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], float tau,
-                                        float sdelta, float gx) {
-  float drho, rho, u, v, uu;
-  lbm::node_moments(g, drho, rho, u, v, uu);
-  if constexpr (FORCED) {
-    u += 0.5f * gx;
-    uu = u * u + v * v;
-  }
+                                        float sdelta, float gx, float drho, float rho, float u,
+                                        float v) {
+  if constexpr (FORCED) u += 0.5f * gx;
+  const float uu = u * u + v * v;
   constexpr float kLog2e = 1.4426950408889634f;
   float sig = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z[0] * kLog2e));
   float tau_adj = 0.5f + sig;
@@ -157,6 +169,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     const int x = xc * 64 + lane;
     const bool valid = x < nx;
     float gp[9];
+    float drho, rho, u, v;  // kept for the collision
     {
       // rows y - 1, y, y + 1 (uniform) and columns x - 1, x, x + 1 (per lane)
       const int xv = valid ? x : nx - 1;
@@ -186,11 +199,10 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
       }
     }
     {
-      float drho, rho, u, v, uu;
-      lbm::node_moments(gp, drho, rho, u, v, uu);
-      if constexpr (WALLS) u += 0.5f * gx;
+      moments(gp, drho, rho, u, v);
+      const float uf = WALLS ? u + 0.5f * gx : u;  // Guo's velocity on the channel
       const float raw[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
-                                gp[6], gp[7], gp[8], drho, u,     v};
+                                gp[6], gp[7], gp[8], drho, uf,    v};
       float ft[NFEAT];
 #pragma unroll
       for (int k = 0; k < NFEAT; ++k) ft[k] = (raw[k] - mu[k]) * isg[k];
@@ -246,19 +258,21 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
         for (int k = 0; k < NOUT; ++k) z[k] = zz[k];
       }
       const float tau = tau_arr ? tau_arr[b] : tau_s;  // b < batch while cw.more()
-      collide<WALLS>(gp, z, tau, sdelta, gx);
+      collide<WALLS>(gp, z, tau, sdelta, gx, drho, rho, u, v);
       float *d = dst + (size_t)b * ny * row + (size_t)y * row + x;
       // node mass in FP32 (rounding ~1e-9 per node, ~1e-13 of the lattice
-      // mass), accumulated over the nodes in FP64
-      float msum = 0.0f;
-      unsigned bad = 0;
+      // mass), accumulated over the nodes in FP64.  A population is negative
+      // or not finite exactly when the smallest f_i is below zero or the sum
+      // is not finite (an infinity or NaN anywhere reaches the sum; the
+      // minimum skips NaN).
+      float msum = 0.0f, fmin = INFINITY;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         __builtin_nontemporal_store(gp[i], d + i * nx);
-        float f = gp[i] + lbm::wgt<float>(i);
-        bad |= (f >= 0.0f && f < INFINITY) ? 0u : 1u;
+        fmin = fminf(fmin, gp[i] + lbm::wgt<float>(i));
         msum += gp[i];
       }
+      const unsigned bad = (fmin >= 0.0f && fabsf(msum) < INFINITY) ? 0u : 1u;
       mass_acc += (double)msum;
       flag_acc |= bad;
       if (head_out) {
