@@ -228,6 +228,9 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     # trained the same way on the same pairs
     tr0, rep0 = train.train(train.DataConfig(), steps=2000, batch=32, rounds=0, data=data)
     f2 = experiments.fixed_error_report(tr0.blob, rounds=0)
+    # which head moves the rollout error (relaxation time or correction)
+    out["head_ablation"] = {"message_passing": experiments.head_ablation(tr.blob, rounds=2),
+                            "fig2_network": experiments.head_ablation(tr0.blob, rounds=0)}
     # the trained per-node network on the forced channel (Poiseuille), the
     # same Reynolds numbers as the BGK channel study
     pois = experiments.poiseuille_study(blob=tr0.blob)

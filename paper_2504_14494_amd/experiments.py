@@ -122,6 +122,32 @@ def fixed_error_report(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_
     return rep
 
 
+def head_ablation(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_fine=512,
+                  n_gnn=128, coarse_steps=(250, 500, 1000)):
+    """Which head of the trained network moves the rollout error: the same
+    fixed-error runs as fixed_error_report with the network as trained, with
+    its relaxation-time head switched off (row 0 of Wh and bh[0] zeroed:
+    z0 = 0, tau_adj = 1 exactly) and with its population correction switched
+    off (s_delta = 0), against the same restricted FP64 reference."""
+    times = sorted({m * (n_fine // n_gnn) for m in coarse_steps})
+    ref = fine_reference(u0, re, phase, n_fine, [n_gnn], times)
+    offs = inputs.blob_offsets(rounds)
+    no_tau = blob.clone()
+    o_wh, (_, wh_cols) = offs["Wh"]
+    o_bh, _ = offs["bh"]
+    no_tau[o_wh:o_wh + wh_cols] = 0.0
+    no_tau[o_bh] = 0.0
+    no_df = blob.clone()
+    no_df[offs["s_delta"][0]] = 0.0
+    out = {"u0": u0, "re": re, "coarse_steps": list(coarse_steps)}
+    for name, b in (("trained", blob), ("tau_head_off", no_tau), ("delta_f_off", no_df)):
+        res, fb, _ = coarse_run(n_gnn, u0, re, phase, list(coarse_steps), b, rounds)
+        out[name] = {"errors": [_rel_err(*res[m], *ref[n_gnn][m * (n_fine // n_gnn)])
+                                for m in coarse_steps], "fallback_steps": fb}
+    return out
+
+
+
 def _energy(ux, uy):
     return 0.5 * float(((ux.double() ** 2) + (uy.double() ** 2)).sum().item())
 

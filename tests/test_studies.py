@@ -96,3 +96,31 @@ def test_stability_sweep_zero_head_equals_bgk_and_follows_analytic_decay():
         assert g["fallback_steps"] == 0 and g["first_fallback_by_step"] is None
         assert abs(g["energy_ratio"] - b["energy_ratio"]) <= 1e-5 * b["energy_ratio"]
         assert abs(b["energy_ratio"] / b["energy_ratio_analytic"] - 1.0) < 1e-2
+
+
+def test_head_ablation_switches_each_head_off():
+    """The ablation runs the network as given, without its relaxation-time
+    head and without its correction.  For a network whose head is only a
+    bias on z0, switching the correction off changes nothing and switching
+    the relaxation time off gives the zero-head (plain BGK) run, bitwise."""
+    blob = inputs.gnn_blob(3, 0, s_delta=1e-2)
+    offs = inputs.blob_offsets(0)
+    o, _ = offs["Wh"]
+    blob[o:o + 650] = 0.0
+    blob[offs["bh"][0]] = 0.3                      # tau_adj = 0.5 + sigmoid(0.3)
+    kw = dict(n_fine=128, n_gnn=32, coarse_steps=(20, 40))
+    rep = experiments.head_ablation(torch.as_tensor(blob, device="cuda"), rounds=0, **kw)
+    bgk = experiments.head_ablation(_zero_head(blob), rounds=0, **kw)
+    assert rep["trained"]["errors"] == rep["delta_f_off"]["errors"]
+    assert rep["tau_head_off"]["errors"] == bgk["trained"]["errors"]
+    assert rep["trained"]["errors"] != rep["tau_head_off"]["errors"]
+    assert all(np.isfinite(rep[k]["errors"]).all() for k in ("trained", "tau_head_off",
+                                                               "delta_f_off"))
+
+
+def _zero_head(blob):
+    b = blob.copy()
+    offs = inputs.blob_offsets(0)
+    o, _ = offs["Wh"]
+    b[o:o + 650] = 0.0
+    return torch.as_tensor(b, device="cuda")
