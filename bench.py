@@ -59,8 +59,8 @@ def bgk_src_hash():
 
 
 def bgk_kernel_name(nx):
-    """The kernel lbm_step_bgk launches for FP32 rows of nx nodes."""
-    return "bgk_pull_wave_kernel" if nx % 64 == 0 else "bgk_pull_kernel<float>"
+    """The kernel lbm_step_bgk launches for FP32 lattices (any width)."""
+    return "bgk_pull_wave_kernel"
 
 
 def simple_src_hash():

@@ -102,7 +102,7 @@ __device__ __forceinline__ float wave_from_right(float v, float halo) {
                                                                0xF, 0xF, false));
 }
 
-// The same step for rows of whole waves (nx a multiple of 64), FP32.  The
+// The same step in FP32, by waves of 64 consecutive nodes of a row.  The
 // six populations that move along x are not gathered from x -/+ 1: every
 // lane loads its own column, so each of the nine loads of a wave covers two
 // whole 128-byte lines, and the values move one lane over through DPP.  The
@@ -113,8 +113,10 @@ __device__ __forceinline__ float wave_from_right(float v, float halo) {
 // read once by one wave and bypass the caches (non-temporal); the six that
 // move keep normal loads, because their edge lines are read again, as a
 // halo, by the neighbouring wave (non-temporal there costs a second HBM
-// fetch of those lines).  Same arithmetic, bitwise the same result as
-// bgk_pull_kernel, about 3% faster at 4096^2 and 8192^2.
+// fetch of those lines).  A row's last wave, when nx is not a multiple of
+// 64, is partial and uses the per-lane gather of bgk_pull_kernel instead.
+// Same arithmetic, bitwise the same result as bgk_pull_kernel, about 3%
+// faster at 4096^2 and 8192^2.
 __global__ __launch_bounds__(kBgkThreads) void bgk_pull_wave_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, int bx,
     float omega) {
@@ -122,8 +124,20 @@ __global__ __launch_bounds__(kBgkThreads) void bgk_pull_wave_kernel(
   const int lane = threadIdx.x & 63;
   const int x0 = __builtin_amdgcn_readfirstlane((blockIdx.x - y * bx) * kBgkThreads +
                                                 (threadIdx.x & ~63));
-  if (x0 >= nx) return;  // whole waves only: every lane of a running wave is active
+  if (x0 >= nx) return;
   const int x = x0 + lane;
+  if (x0 + 64 > nx) {
+    // the row's last wave is partial: the per-lane gather (no lane shifts)
+    if (x >= nx) return;
+    float g[9];
+    pull9(src, nx, ny, x, y, g);
+    bgk_collide(g, omega);
+    float *d = dst + (size_t)y * 9 * nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(g[i], d + (size_t)i * nx);
+    return;
+  }
+  // from here every lane of the wave is active, as the lane shifts need
   const int xl = x0 == 0 ? nx - 1 : x0 - 1;
   const int xr = x0 + 64 == nx ? 0 : x0 + 64;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
@@ -159,11 +173,9 @@ int launch_bgk(const T *src, T *dst, int nx, int ny, T tau, hipStream_t s) {
   long long blocks = (long long)bx * ny;
   if (blocks > 0x7fffffffLL) return fail(LBM_EINVAL, "lbm_step_bgk: lattice too large");
   if constexpr (sizeof(T) == sizeof(float)) {
-    if (nx % 64 == 0) {
-      hipLaunchKernelGGL(bgk_pull_wave_kernel, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s,
-                         src, dst, nx, ny, bx, T(1) / tau);
-      return launch_check("bgk_pull_wave_kernel");
-    }
+    hipLaunchKernelGGL(bgk_pull_wave_kernel, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s,
+                       src, dst, nx, ny, bx, T(1) / tau);
+    return launch_check("bgk_pull_wave_kernel");
   }
   hipLaunchKernelGGL(bgk_pull_kernel<T>, dim3((unsigned)blocks), dim3(kBgkThreads), 0, s, src,
                      dst, nx, ny, bx, T(1) / tau);
