@@ -187,14 +187,14 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
             // a population that would come through a wall is the reversed one
             // that left this node (the row is uniform over the wave)
             if ((cy(i) > 0 && y == 0) || (cy(i) < 0 && y == ny - 1))
-              gp[i] = r1[lbm::opp(i) * nx + xv];
+              gp[i] = r1[(size_t)lbm::opp(i) * nx + xv];
             else
-              gp[i] = r[i * nx + xsrc];
+              gp[i] = r[(size_t)i * nx + xsrc];
           } else {
-            gp[i] = r[i * nx + xsrc];
+            gp[i] = r[(size_t)i * nx + xsrc];
           }
         } else {
-          gp[i] = r1[i * nx + xv];
+          gp[i] = r1[(size_t)i * nx + xv];
         }
       }
     }
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
       float msum = 0.0f, fmin = INFINITY;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        __builtin_nontemporal_store(gp[i], d + i * nx);
+        __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
         fmin = fminf(fmin, gp[i] + lbm::wgt<float>(i));
         msum += gp[i];
       }
