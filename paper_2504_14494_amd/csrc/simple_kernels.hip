@@ -151,11 +151,12 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
   }
   const float *cst = (const float *)(pack + F.const_off);
   const float sdelta = cst[C_SDELTA];
-  float mu[NFEAT], isg[NFEAT];
+  // normalisation (x - mu) / sigma as one FMA per feature: x * isg + nmi
+  float isg[NFEAT], nmi[NFEAT];
 #pragma unroll
   for (int k = 0; k < NFEAT; ++k) {
-    mu[k] = cst[C_MU + k];
     isg[k] = 1.0f / cst[C_SIGMA + k];
+    nmi[k] = -cst[C_MU + k] * isg[k];
   }
   __syncthreads();
   uint32_t *sw = slot_s[wave];
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
                                 gp[6], gp[7], gp[8], drho, uf,    v};
       float ft[NFEAT];
 #pragma unroll
-      for (int k = 0; k < NFEAT; ++k) ft[k] = (raw[k] - mu[k]) * isg[k];
+      for (int k = 0; k < NFEAT; ++k) ft[k] = fmaf(raw[k], isg[k], nmi[k]);
       u32x4 *o = (u32x4 *)(sw + lane * kSlot);
       o[0] = u32x4{pack_bf16(ft[0], ft[1]), pack_bf16(ft[2], ft[3]), pack_bf16(ft[4], ft[5]),
                    pack_bf16(ft[6], ft[7])};
