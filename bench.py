@@ -228,6 +228,14 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     # trained the same way on the same pairs
     tr0, rep0 = train.train(train.DataConfig(), steps=2000, batch=32, rounds=0, data=data)
     f2 = experiments.fixed_error_report(tr0.blob, rounds=0)
+    # the validation section's table: errors against the analytic vortex at
+    # 1000/3000/5000 steps, 64^2, Re = 100, for both starts
+    tv = {}
+    for start in ("equilibrium", "slow"):
+        for name, b, rr in (("bgk", None, 2), ("gnn", tr.blob, 2), ("fig2_network", tr0.blob, 0)):
+            rep_tv = experiments.tgv_validation(b, rounds=rr, start=start)
+            tv[f"{name}_{start}_start"] = [float(f"{r['vel_err']:.4g}") for r in rep_tv["rows"]]
+    out["tgv_validation_64_re100"] = {"steps": [1000, 3000, 5000], **tv}
     # which head moves the rollout error (relaxation time or correction)
     out["head_ablation"] = {"message_passing": experiments.head_ablation(tr.blob, rounds=2),
                             "fig2_network": experiments.head_ablation(tr0.blob, rounds=0)}

@@ -285,6 +285,36 @@ def resolution_study(blob=None, rounds=2, re=100.0, sizes=(32, 64, 128), scaling
     return {"re": re, "scaling": scaling, "fp64": fp64, "rows": rows, "alpha": alpha}
 
 
+def tgv_validation(blob=None, rounds=2, n=64, re=100.0, u0=0.04, checkpoints=(1000, 3000, 5000),
+                   start="equilibrium"):
+    """Velocity (L2, R5) and energy errors against the analytic vortex at the
+    given step counts on one lattice (the validation section's table of
+    errors at 1000, 3000 and 5000 steps, 64^2, Re = 100).  start
+    "equilibrium": f = f^eq(1, u) with uniform density (the workload's
+    definition), which launches an acoustic transient the error then
+    carries; "slow": the Chapman-Enskog state with the Taylor-Green pressure.
+    BGK when blob is None, else the corrected collision with the gate."""
+    if start not in ("equilibrium", "slow"):
+        raise ValueError("start must be 'equilibrium' or 'slow'")
+    tau32 = float(np.float32(_tau(u0, re, n)))
+    if start == "slow":
+        lat = _lattice(n, u0, tau32, blob, rounds)
+    else:
+        rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
+        lat = (lbm.Lattice(n, n) if blob is None else gnn.GnnLattice(n, n, blob, rounds))
+        lat.init(rho, ux, uy)
+    rows, done = [], 0
+    for t in sorted(checkpoints):
+        _advance(lat, blob, tau32, t - done)
+        done = t
+        row = {"steps": t}
+        row.update(tgv_state_errors(lat.a, n, u0, tau32, t))
+        if blob is not None:
+            row["fallback_steps"] = int(lat.n_fallback.item())
+        rows.append(row)
+    return {"n": n, "re": re, "u0": u0, "tau": tau32, "start": start, "rows": rows}
+
+
 def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
                     re_list=(100, 200, 400, 800, 1600, 3200), steps=20000, every=1000):
     """Taylor-Green runs on an n^2 lattice over a range of Reynolds numbers.
@@ -379,7 +409,7 @@ def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
 def main(argv=None):
     """Runs one study and prints its report as JSON:
     python -m paper_2504_14494_amd.experiments {fixed-error, resolution,
-    stability, poiseuille, long-rollout} [--rounds R].  The corrected-collision
+    stability, poiseuille, long-rollout, tgv-validation} [--rounds R].  The corrected-collision
     studies first train the network (train.train, full configuration); the
     Poiseuille study runs a network only with --rounds 0 (the per-node
     network has no neighbours across a wall; message passing has no wall
@@ -391,7 +421,7 @@ def main(argv=None):
     from . import train
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["fixed-error", "resolution", "stability", "poiseuille",
-                                      "long-rollout"])
+                                      "long-rollout", "tgv-validation"])
     ap.add_argument("--rounds", type=int, default=2, help="2: message passing; 0: Fig. 2")
     ap.add_argument("--scaling", default="diffusive", choices=["diffusive", "acoustic"])
     ap.add_argument("--fp64", action="store_true", help="BGK runs in FP64 (resolution, poiseuille)")
@@ -399,7 +429,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     t0 = time.perf_counter()
     blob = None
-    if args.study in ("fixed-error", "stability", "long-rollout") or (
+    if args.study in ("fixed-error", "stability", "long-rollout", "tgv-validation") or (
             args.study == "resolution" and not args.fp64) or (
             args.study == "poiseuille" and args.rounds == 0 and not args.fp64):
         tr, rep = train.train(train.DataConfig(), steps=2000, batch=32, rounds=args.rounds)
@@ -416,6 +446,9 @@ def main(argv=None):
         out = {"bgk": poiseuille_study(fp64=args.fp64)}
         if blob is not None:
             out["fig2_network"] = poiseuille_study(blob=blob)
+    elif args.study == "tgv-validation":
+        out = {f"{name}_{start}_start": tgv_validation(b, rounds=args.rounds, start=start)
+               for start in ("equilibrium", "slow") for name, b in (("bgk", None), ("gnn", blob))}
     else:
         out = long_rollout(blob, rounds=args.rounds, steps=args.steps)
     out["wall_seconds"] = round(time.perf_counter() - t0, 1)

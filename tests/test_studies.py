@@ -124,3 +124,24 @@ def _zero_head(blob):
     o, _ = offs["Wh"]
     b[o:o + 650] = 0.0
     return torch.as_tensor(b, device="cuda")
+
+
+def test_tgv_validation_bgk_matches_the_oracle(orc):
+    """The validation table's BGK run (64^2, Re = 100, equilibrium start):
+    its velocity error against the analytic vortex at 1000 steps equals the
+    FP64 oracle's error of the same run.  By the triangle inequality the two
+    errors differ by at most ||u_gpu - u_oracle|| / ||u_a||, which the FP32
+    step's parity bar (1e-5 relative after 1000 steps) bounds."""
+    rep = experiments.tgv_validation(None, checkpoints=(1000,))
+    n, u0 = 64, 0.04
+    tau = rep["tau"]
+    rho, ux, uy = inputs.tgv_velocity(n, n, u0)
+    f = orc.bgk_run(orc.init_equilibrium(np.ones_like(rho), ux, uy), tau, 1000)
+    _, vx, vy = orc.moments(f)
+    nu, k = (tau - 0.5) / 3.0, 2 * math.pi / n
+    decay = math.exp(-2 * nu * k * k * 1000)
+    ax, ay = ux * decay, uy * decay
+    err = math.sqrt((((vx - ax) ** 2 + (vy - ay) ** 2).sum()) / ((ax ** 2 + ay ** 2).sum()))
+    got = rep["rows"][0]["vel_err"]
+    print(f"velocity error at 1000 steps: GPU {got:.6e}, oracle {err:.6e}")
+    assert abs(got - err) <= 1e-5
