@@ -429,21 +429,43 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
         an[t] = mfma(wa[(2 * t + 1) * 64], hn[1], an[t]);
       }
       f32x4 T[4] = {};
-#pragma unroll 2
+      // The eight neighbours' states, every load issued before the first is
+      // used.  The edge loop is unrolled in full, so the direction of each
+      // edge (its wrap, its edge feature, the sign it adds to the Wc
+      // gradients with) is a compile-time constant and the loop has no
+      // branches to split its schedule.
+      u32x4 hj[8][2];
+#pragma unroll
       for (int d = 1; d < 9; ++d) {
         int xj = P.x + cx(d), yj = P.y + cy(d);
         xj = xj < 0 ? xj + nx : (xj >= nx ? xj - nx : xj);
         yj = yj < 0 ? yj + ny : (yj >= ny ? yj - ny : yj);
-        u32x4 hj[2];
-        load_frags(h, lat_nodes + (size_t)yj * nx + xj, q, hj);
-        const u32x4 ed = {q == 0 ? (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)) : 0u, 0u, 0u,
-                          0u};
+        load_frags(h, lat_nodes + (size_t)yj * nx + xj, q, hj[d - 1]);
+      }
+      const uint32_t q0 = q == 0 ? 0xffffffffu : 0u;
+      // pre-activation of the message from direction d (MFMA only)
+      auto message = [&](int d, f32x4(&a)[4]) {
+        const u32x4 ed = {q0 & (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)), 0u, 0u, 0u};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[t] = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
+          a[t] = mfma(wb[t][0], hj[d - 1][0], a[t]);
+          a[t] = mfma(wb[t][1], hj[d - 1][1], a[t]);
+        }
+      };
+      // Software pipeline as in the forward round: the MFMA chains of edge
+      // d + 1 are issued among the VALU work of edge d (one wave per SIMD
+      // here, so nothing else fills the matrix-core latency).  The sums run
+      // over d in the same order as without the pipeline.
+      f32x4 pre[2][4];
+      message(1, pre[1]);
+#pragma unroll
+      for (int d = 1; d < 9; ++d) {
+        if (d < 8) message(d + 1, pre[(d + 1) & 1]);
         f32x4 dq[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          f32x4 a = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
-          a = mfma(wb[t][0], hj[0], a);
-          a = mfma(wb[t][1], hj[1], a);
+          const f32x4 a = pre[d & 1][t];
           dq[t] = da[t] * f32x4{gelu_grad(a.x), gelu_grad(a.y), gelu_grad(a.z), gelu_grad(a.w)};
           T[t] += dq[t];
           if (cx(d) > 0) vxs[t] += dq[t];
@@ -455,6 +477,14 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
           u32x4 *o = (u32x4 *)(dq_out + (P.node * 8 + (d - 1)) * HID);
           o[q] = frag_from_acc(dq[0], dq[1]);
           o[4 + q] = frag_from_acc(dq[2], dq[3]);
+        }
+        if (d < 8) {
+          // each of edge d + 1's 12 MFMAs followed by 10 VALU instructions
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+          }
         }
       }
       const u32x4 tb[2] = {frag_from_acc(T[0], T[1]), frag_from_acc(T[2], T[3])};
