@@ -82,13 +82,17 @@ __device__ __forceinline__ float gelu(float x) {
   return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
-// d GELU / dx = s - x s (1 - s) ln2 (A + 3 B x^2), s = 1 / (1 + 2^t).
+// d GELU / dx = s - x s (1 - s) ln2 (A + 3 B x^2), s = 1 / (1 + 2^t),
+// evaluated as s (1 - w + w s) with w = x ln2 (A + 3 B x^2) and ln2 folded
+// into the constants: 11 VALU instructions, two of them transcendental.
+constexpr float kGeluDA = kGeluA * kLn2;
+constexpr float kGeluDB = 3.0f * kGeluB * kLn2;
 __device__ __forceinline__ float gelu_grad(float x) {
   float x2 = x * x;
   float t = x * __builtin_fmaf(x2, kGeluB, kGeluA);
   float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
-  float dt = __builtin_fmaf(x2, 3.0f * kGeluB, kGeluA) * kLn2;
-  return s - x * s * (1.0f - s) * dt;
+  float w = x * __builtin_fmaf(x2, kGeluDB, kGeluDA);
+  return s * __builtin_fmaf(w, s, 1.0f - w);
 }
 
 __device__ __forceinline__ f32x4 gelu4(f32x4 v) {
