@@ -375,13 +375,45 @@ __global__ __launch_bounds__(kBT) void bwd_node_kernel(
 
 // --------------------------------------------- edge layer, receiver side ---
 
-// dq_{n,d} (stored BF16), T_n, dWa, dbe, dWc; dh_n += Wa^T T_n.
+// Node states of one 16-receiver group and its ring (3 rows x 18 columns),
+// staged in LDS: node ln = 18 hy + hx at byte 144 ln (128 B of state and 16
+// B of padding, so that 16 lanes reading one 16-byte chunk of 16 consecutive
+// nodes hit 16 disjoint groups of banks).  One direct-to-LDS load of a wave
+// fills 64 16-byte slots, node ln's chunk c at slot 9 ln + c.
+constexpr int kRingX = 18, kRingY = 3, kRingNodes = kRingX * kRingY;
+constexpr int kRingNodeBytes = 144;
+constexpr int kRingLoads = (kRingNodes * 9 + 63) / 64;
+constexpr int kRingBytes = kRingLoads * 64 * 16;
+// slot / 9 and node / 18 by multiply and shift, exact over the whole range
+constexpr int kRingDiv9 = 7282, kRingDiv18 = 3641;
+constexpr bool ring_divisions_exact() {
+  for (int v = 0; v < kRingLoads * 64; ++v)
+    if (((v * kRingDiv9) >> 16) != v / 9) return false;
+  for (int v = 0; v < kRingNodes; ++v)
+    if (((v * kRingDiv18) >> 16) != v / kRingX) return false;
+  return true;
+}
+static_assert(kRingNodeBytes == 9 * 16 && ring_divisions_exact(), "ring staging");
+// s_waitcnt vmcnt(0) with expcnt and lgkmcnt left at their maximum.
+constexpr int kBwdWaitVmcnt0 = 0x0F70;
+
+// dq_{n,d} (stored BF16), T_n, dWa, dbe, dWc; Wa^T T_n over dL/dagg_n.
+// One wave per SIMD (the kernel needs 400+ registers), so memory latency is
+// hidden by prefetching instead of by other waves: while a wave works on one
+// group of 16 receivers, direct-to-LDS loads bring the next group's node
+// states and ring into the wave's other LDS buffer, and the next group's
+// dL/dagg rows come into registers.  One explicit wait late in each
+// group (vmcnt counts loads and stores together, so it also drains the
+// group's earlier stores, long complete by then) covers all of them.  The
+// arithmetic and its order are those of the direct loads.
 __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
-    const float *__restrict__ dagg, const uint16_t *__restrict__ h, int batch, int nx, int ny,
+    float *__restrict__ dagg_io, const uint16_t *__restrict__ h, int batch, int nx, int ny,
     int r, const uint8_t *__restrict__ pack, FragLayout F, BlobLayout L,
-    uint16_t *__restrict__ dq_out, float *__restrict__ dh, float *__restrict__ part) {
+    uint16_t *__restrict__ dq_out, float *__restrict__ part) {
+  const float *dagg = dagg_io;
   __shared__ Stage<64, 64> st[4];
   __shared__ u32x4 wa_s[8 * 64], wat_s[8 * 64];
+  __shared__ __attribute__((aligned(16))) uint8_t ring_s[4][2][kRingBytes];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
   Stage<64, 64> &S = st[wave];
@@ -405,43 +437,82 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
   const long long gxn = (nx + 15) / 16, ngroups = (long long)batch * ny * gxn;
   const long long nchunks = (ngroups + 1) / 2;
   const int w = blockIdx.x * 4 + wave;
+
+  // Issues the loads of group `grp` (clamped as group_pos clamps it): its
+  // ring into `buf` (direct to LDS, wrapped at the lattice edges; slots past
+  // the last node repeat its last chunk) and its dL/dagg rows into registers.
+  auto prefetch = [&](long long grp, uint8_t *buf, f32x4(&da)[4]) {
+    const Pos P = group_pos(grp, ngroups, n, nx, ny, gxn);
+    const int x0 = (int)((grp < ngroups ? grp : 0) % gxn) * 16;
+    const size_t lat_nodes = (size_t)P.b * ny * nx;
+#pragma unroll
+    for (int k = 0; k < kRingLoads; ++k) {
+      const unsigned slot = 64 * k + lane;
+      unsigned ln = __umul24(slot, kRingDiv9) >> 16;
+      unsigned c = slot - 9 * ln;
+      if (ln >= (unsigned)kRingNodes) {
+        ln = kRingNodes - 1;
+        c = 7;
+      }
+      c = c < 7 ? c : 7;
+      const int hy = (int)(__umul24(ln, kRingDiv18) >> 16);
+      const int hx = (int)ln - kRingX * hy;
+      int gx = x0 - 1 + hx, gy = P.y - 1 + hy;
+      gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+      gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+      if (gx >= nx) gx %= nx;  // lattices narrower than the ring
+      if (gy >= ny) gy %= ny;
+      const uint16_t *src = h + (lat_nodes + (size_t)gy * nx + gx) * HID + c * 8;
+      __builtin_amdgcn_global_load_lds((const void *)src,
+                                       (__attribute__((address_space(3))) void *)(buf + k * 1024),
+                                       16, 0, 0);
+    }
+    load_acc(dagg, P.node, q, da);
+  };
+
   f32x4 acc[4][4] = {};
   f32x4 tsum[4] = {}, vxs[4] = {}, vys[4] = {};
-  for (long long c = w; c < nchunks; c += kBwdWaves) {
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
+  f32x4 da_nx[4];
+  // One group: half 0 or 1 of chunk c, its ring in `cur`; the next group's
+  // loads go to `nxt`.
+  auto group = [&](long long c, int half, const uint8_t *cur, uint8_t *nxt) {
       int wo = lane;
       asm volatile("" : "+v"(wo));
       const u32x4 *wa = wa_s + wo, *wat = wat_s + wo;
-      Pos P = group_pos(2 * c + half, ngroups, n, nx, ny, gxn);
-      const size_t lat_nodes = (size_t)P.b * ny * nx;
-      u32x4 hn[2];
-      load_frags(h, P.node, q, hn);
+      const Pos P = group_pos(2 * c + half, ngroups, n, nx, ny, gxn);
+      // (zero on lanes outside the lattice)
       f32x4 da[4];
-      load_acc(dagg, P.node, q, da);
-      if (!P.valid)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) da[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int t = 0; t < 4; ++t) da[t] = P.valid ? da_nx[t] : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      // the next group of this wave: the chunk's second half, or the first
+      // half of the wave's next chunk
+      // chunk q of this receiver's lower-left neighbour; every neighbour's
+      // chunk is at a constant offset from it
+      const uint8_t *nb = cur + n * kRingNodeBytes + q * 16;
+      auto frag_at = [&](int dx, int dy, int sidx) {
+        return *(const u32x4 *)(nb + ((dy + 1) * kRingX + dx + 1) * kRingNodeBytes + sidx * 64);
+      };
+      // all of the group's ring reads, before the next group's loads
+      const u32x4 hn[2] = {frag_at(0, 0, 0), frag_at(0, 0, 1)};
+      u32x4 hj[8][2];
+#pragma unroll
+      for (int d = 1; d < 9; ++d) {
+        hj[d - 1][0] = frag_at(cx(d), cy(d), 0);
+        hj[d - 1][1] = frag_at(cx(d), cy(d), 1);
+      }
       f32x4 an[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         an[t] = mfma(wa[(2 * t) * 64], hn[0], be[t]);
         an[t] = mfma(wa[(2 * t + 1) * 64], hn[1], an[t]);
       }
+      const long long next = half == 0 ? 2 * c + 1 : 2 * (c + kBwdWaves);
+      if (half == 0 || c + kBwdWaves < nchunks) prefetch(next, nxt, da_nx);
       f32x4 T[4] = {};
-      // The eight neighbours' states, every load issued before the first is
-      // used.  The edge loop is unrolled in full, so the direction of each
-      // edge (its wrap, its edge feature, the sign it adds to the Wc
-      // gradients with) is a compile-time constant and the loop has no
-      // branches to split its schedule.
-      u32x4 hj[8][2];
-#pragma unroll
-      for (int d = 1; d < 9; ++d) {
-        int xj = P.x + cx(d), yj = P.y + cy(d);
-        xj = xj < 0 ? xj + nx : (xj >= nx ? xj - nx : xj);
-        yj = yj < 0 ? yj + ny : (yj >= ny ? yj - ny : yj);
-        load_frags(h, lat_nodes + (size_t)yj * nx + xj, q, hj[d - 1]);
-      }
+      // The edge loop is unrolled in full, so the direction of each edge (its
+      // edge feature, the sign it adds to the Wc gradients with) is a
+      // compile-time constant and the loop has no branches to split its
+      // schedule.
       const uint32_t q0 = q == 0 ? 0xffffffffu : 0u;
       // pre-activation of the message from direction d (MFMA only)
       auto message = [&](int d, f32x4(&a)[4]) {
@@ -473,6 +544,10 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
           if (cy(d) > 0) vys[t] += dq[t];
           if (cy(d) < 0) vys[t] -= dq[t];
         }
+        // The next group's loads were issued at the start of this one: wait
+        // for them here, where they have had most of the group to land.
+        // Unconditional, so the compiler also counts them as complete.
+        if (d == 6) __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
         if (P.valid) {
           u32x4 *o = (u32x4 *)(dq_out + (P.node * 8 + (d - 1)) * HID);
           o[q] = frag_from_acc(dq[0], dq[1]);
@@ -495,11 +570,24 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
         o[t] = mfma(wat[(2 * t + 1) * 64], tb[1], o[t]);
         tsum[t] += T[t];
       }
-      if (P.valid) add_acc(dh, P.node, q, o);
+      // Wa^T T replaces this group's dL/dagg rows, read by nobody after
+      // this group; the sender-side kernel adds it to dh.
+      if (P.valid) store_acc(dagg_io, P.node, q, o);
       const int col = 16 * half + n;
       stage_acc(S.d, T, q, col);
       stage_frag(S.a, hn, q, col);
-    }
+  };
+
+  // Group i of this wave works from ring_s[wave][i % 2].  The compiler
+  // cannot tell the two buffers apart, so it would wait for loads in flight
+  // into one before any LDS read: each group therefore does all its ring and
+  // Wa reads before it issues the next group's loads, and reads LDS again
+  // only after its explicit wait.
+  if (w < nchunks) prefetch(2 * (long long)w, ring_s[wave][0], da_nx);
+  __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
+  for (long long c = w; c < nchunks; c += kBwdWaves) {
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) group(c, half, ring_s[wave][half], ring_s[wave][half ^ 1]);
     wave_lds_sync();
     dw_mma<4, 4>(acc, S.d, S.a, lane);
     wave_lds_sync();
@@ -513,11 +601,12 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
 
 // ----------------------------------------------- edge layer, sender side ---
 
-// S_m = sum_d dq_{m - e_d, d}; dWb; dh_m += Wb^T S_m.
+// S_m = sum_d dq_{m - e_d, d}; dWb; dh_m += Wa^T T_m (left by the receiver
+// side in orecv), then dh_m += Wb^T S_m.
 __global__ __launch_bounds__(kBT) void bwd_edge_send_kernel(
     const uint16_t *__restrict__ dq_in, const uint16_t *__restrict__ h, int batch, int nx,
     int ny, int r, const uint8_t *__restrict__ pack, FragLayout F, BlobLayout L,
-    float *__restrict__ dh, float *__restrict__ part) {
+    const float *__restrict__ orecv, float *__restrict__ dh, float *__restrict__ part) {
   __shared__ Stage<64, 64> st[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
@@ -562,7 +651,12 @@ __global__ __launch_bounds__(kBT) void bwd_edge_send_kernel(
         o[t] = mfma(wbt[t][0], sb[0], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
         o[t] = mfma(wbt[t][1], sb[1], o[t]);
       }
-      if (P.valid) add_acc(dh, P.node, q, o);
+      if (P.valid) {
+        f32x4 *p = (f32x4 *)(dh + P.node * HID) + q * 4;
+        const f32x4 *pr = (const f32x4 *)(orecv + P.node * HID) + q * 4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p[t] = (p[t] + pr[t]) + o[t];
+      }
       u32x4 hm[2];
       load_frags(h, P.node, q, hm);
       const int col = 16 * half + n;
@@ -787,10 +881,10 @@ extern "C" int gnn_backward(const float *dL_dgpost, const float *g_pre, const vo
                        asaved(r), batch, nx, ny, r, pack, F, L, dout, dagg, part);
     if (int rc = launch_check("bwd_node_kernel")) return rc;
     hipLaunchKernelGGL(bwd_edge_recv_kernel, dim3(kBwdBlocks), dim3(kBT), 0, s, dagg, hsaved(r),
-                       batch, nx, ny, r, pack, F, L, dq, dout, part);
+                       batch, nx, ny, r, pack, F, L, dq, part);
     if (int rc = launch_check("bwd_edge_recv_kernel")) return rc;
     hipLaunchKernelGGL(bwd_edge_send_kernel, dim3(kBwdBlocks), dim3(kBT), 0, s, dq, hsaved(r),
-                       batch, nx, ny, r, pack, F, L, dout, part);
+                       batch, nx, ny, r, pack, F, L, dagg, dout, part);
     if (int rc = launch_check("bwd_edge_send_kernel")) return rc;
     cur ^= 1;
   }
