@@ -186,6 +186,9 @@ __device__ __forceinline__ void write_vec(float *part, size_t base, int stride,
   wave_lds_sync();
 }
 
+// s_waitcnt vmcnt(0) with expcnt and lgkmcnt left at their maximum.
+constexpr int kBwdWaitVmcnt0 = 0x0F70;
+
 template <int DR, int AR>
 struct Stage {
   uint16_t d[DR * kPitch];
@@ -322,6 +325,21 @@ __global__ __launch_bounds__(kBT) void bwd_node_kernel(
   const int w = blockIdx.x * 4 + wave;
   f32x4 acc[4][8] = {};
   f32x4 bsum[4] = {};
+  // One wave per SIMD: each group's node state, aggregate and incoming
+  // gradient are loaded while the previous group is computed, and one
+  // explicit wait before the group's first store covers them (vmcnt counts
+  // loads and stores together; waiting there, the loads have had most of the
+  // group to land and the previous group's stores are long complete).
+  u32x4 hf_nx[2], af_nx[2];
+  f32x4 G_nx[4];
+  auto prefetch = [&](long long grp) {
+    const Pos P = group_pos(grp, ngroups, n, nx, ny, gxn);
+    load_frags(h, P.node, q, hf_nx);
+    load_frags(agg, P.node, q, af_nx);
+    load_acc(dh_in, P.node, q, G_nx);
+  };
+  if (w < nchunks) prefetch(2 * (long long)w);
+  __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
   for (long long c = w; c < nchunks; c += kBwdWaves) {
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
@@ -329,11 +347,10 @@ __global__ __launch_bounds__(kBT) void bwd_node_kernel(
       asm volatile("" : "+v"(wo));
       const u32x4 *wn = wn_s + wo, *wnt = wnt_s + wo;
       Pos P = group_pos(2 * c + half, ngroups, n, nx, ny, gxn);
-      u32x4 hf[2], af[2];
-      load_frags(h, P.node, q, hf);
-      load_frags(agg, P.node, q, af);
-      f32x4 G[4];
-      load_acc(dh_in, P.node, q, G);
+      const u32x4 hf[2] = {hf_nx[0], hf_nx[1]}, af[2] = {af_nx[0], af_nx[1]};
+      const f32x4 G[4] = {G_nx[0], G_nx[1], G_nx[2], G_nx[3]};
+      if (half == 0 || c + kBwdWaves < nchunks)
+        prefetch(half == 0 ? 2 * c + 1 : 2 * (c + kBwdWaves));
       f32x4 dp[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -353,6 +370,7 @@ __global__ __launch_bounds__(kBT) void bwd_node_kernel(
         o[t] = mfma(wnt[(2 * t) * 64], dpb[0], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
         o[t] = mfma(wnt[(2 * t + 1) * 64], dpb[1], o[t]);
       }
+      __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
       if (P.valid) {
         const f32x4 o_h[4] = {o[0], o[1], o[2], o[3]};
         const f32x4 o_a[4] = {o[4], o[5], o[6], o[7]};
@@ -394,8 +412,6 @@ constexpr bool ring_divisions_exact() {
   return true;
 }
 static_assert(kRingNodeBytes == 9 * 16 && ring_divisions_exact(), "ring staging");
-// s_waitcnt vmcnt(0) with expcnt and lgkmcnt left at their maximum.
-constexpr int kBwdWaitVmcnt0 = 0x0F70;
 
 // dq_{n,d} (stored BF16), T_n, dWa, dbe, dWc; Wa^T T_n over dL/dagg_n.
 // One wave per SIMD (the kernel needs 400+ registers), so memory latency is
