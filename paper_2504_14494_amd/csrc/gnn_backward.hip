@@ -638,24 +638,57 @@ __global__ __launch_bounds__(kBT) void bwd_edge_send_kernel(
   const long long nchunks = (ngroups + 1) / 2;
   const int w = blockIdx.x * 4 + wave;
   f32x4 acc[4][4] = {};
+  // One wave per SIMD: the next group's dq rows (eight directions), node
+  // state, dh and the receiver side's term are loaded while this group is
+  // computed; one explicit wait before the group's store covers them.
+  u32x4 dq_nx[8][2], hm_nx[2];
+  f32x4 dh_nx[4], or_nx[4];
+  auto prefetch = [&](long long grp) {
+    const Pos P = group_pos(grp, ngroups, n, nx, ny, gxn);
+    const size_t lat_nodes = (size_t)P.b * ny * nx;
+#pragma unroll
+    for (int d = 1; d < 9; ++d) {
+      int xn = P.x - cx(d), yn = P.y - cy(d);  // receiver whose edge d points here
+      xn = xn < 0 ? xn + nx : (xn >= nx ? xn - nx : xn);
+      yn = yn < 0 ? yn + ny : (yn >= ny ? yn - ny : yn);
+      const u32x4 *src =
+          (const u32x4 *)(dq_in + ((lat_nodes + (size_t)yn * nx + xn) * 8 + (d - 1)) * HID);
+      dq_nx[d - 1][0] = src[q];
+      dq_nx[d - 1][1] = src[4 + q];
+    }
+    load_frags(h, P.node, q, hm_nx);
+    load_acc(dh, P.node, q, dh_nx);
+    load_acc(orecv, P.node, q, or_nx);
+  };
+  if (w < nchunks) prefetch(2 * (long long)w);
+  __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
   for (long long c = w; c < nchunks; c += kBwdWaves) {
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
       Pos P = group_pos(2 * c + half, ngroups, n, nx, ny, gxn);
-      const size_t lat_nodes = (size_t)P.b * ny * nx;
+      u32x4 dqc[8][2], hm[2];
+      f32x4 dhc[4], orc[4];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        dqc[d][0] = dq_nx[d][0];
+        dqc[d][1] = dq_nx[d][1];
+      }
+      hm[0] = hm_nx[0];
+      hm[1] = hm_nx[1];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        dhc[t] = dh_nx[t];
+        orc[t] = or_nx[t];
+      }
+      if (half == 0 || c + kBwdWaves < nchunks)
+        prefetch(half == 0 ? 2 * c + 1 : 2 * (c + kBwdWaves));
       f32x4 Sm[4] = {};
 #pragma unroll
-      for (int d = 1; d < 9; ++d) {
-        int xn = P.x - cx(d), yn = P.y - cy(d);  // receiver whose edge d points here
-        xn = xn < 0 ? xn + nx : (xn >= nx ? xn - nx : xn);
-        yn = yn < 0 ? yn + ny : (yn >= ny ? yn - ny : yn);
-        const u32x4 *src =
-            (const u32x4 *)(dq_in + ((lat_nodes + (size_t)yn * nx + xn) * 8 + (d - 1)) * HID);
-        u32x4 f0 = src[q], f1 = src[4 + q];
-        Sm[0] += unpack_lo(f0);
-        Sm[1] += unpack_hi(f0);
-        Sm[2] += unpack_lo(f1);
-        Sm[3] += unpack_hi(f1);
+      for (int d = 0; d < 8; ++d) {
+        Sm[0] += unpack_lo(dqc[d][0]);
+        Sm[1] += unpack_hi(dqc[d][0]);
+        Sm[2] += unpack_lo(dqc[d][1]);
+        Sm[3] += unpack_hi(dqc[d][1]);
       }
       if (!P.valid)
 #pragma unroll
@@ -667,14 +700,12 @@ __global__ __launch_bounds__(kBT) void bwd_edge_send_kernel(
         o[t] = mfma(wbt[t][0], sb[0], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
         o[t] = mfma(wbt[t][1], sb[1], o[t]);
       }
+      __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
       if (P.valid) {
         f32x4 *p = (f32x4 *)(dh + P.node * HID) + q * 4;
-        const f32x4 *pr = (const f32x4 *)(orecv + P.node * HID) + q * 4;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) p[t] = (p[t] + pr[t]) + o[t];
+        for (int t = 0; t < 4; ++t) p[t] = (dhc[t] + orc[t]) + o[t];
       }
-      u32x4 hm[2];
-      load_frags(h, P.node, q, hm);
       const int col = 16 * half + n;
       stage_acc(S.d, Sm, q, col);
       stage_frag(S.a, hm, q, col);
