@@ -812,12 +812,17 @@ __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
   write_vec(pw, L.b1, 1, s1, S.red, lane);
 }
 
-// Fixed-order sum of the per-wave partials.
-__global__ __launch_bounds__(kBT) void bwd_reduce_kernel(const float *__restrict__ part,
-                                                         size_t nparam, float *__restrict__ grad) {
-  size_t p = (size_t)blockIdx.x * kBT + threadIdx.x;
+// Fixed-order sum of the per-wave partials: one thread per parameter, the
+// partials added in wave order.  One-wave blocks spread the ~600 waves over
+// every CU, and the unrolled loop keeps 32 independent loads in flight ahead
+// of the (sequential) additions.
+constexpr int kReduceThreads = 64;
+__global__ __launch_bounds__(kReduceThreads) void bwd_reduce_kernel(
+    const float *__restrict__ part, size_t nparam, float *__restrict__ grad) {
+  size_t p = (size_t)blockIdx.x * kReduceThreads + threadIdx.x;
   if (p >= nparam) return;
   float s = 0.0f;
+#pragma unroll 32
   for (int w = 0; w < kBwdWaves; ++w) s += part[(size_t)w * nparam + p];
   grad[p] = s;
 }
@@ -945,8 +950,9 @@ extern "C" int gnn_backward(const float *dL_dgpost, const float *g_pre, const vo
                        (const uint16_t *)at(saved, SL.x), (const uint16_t *)at(saved, SL.e1),
                        batch, nx, ny, pack, F, L, part);
   if (int rc = launch_check("bwd_encoder_kernel")) return rc;
-  hipLaunchKernelGGL(bwd_reduce_kernel, dim3((unsigned)((L.nparam + kBT - 1) / kBT)), dim3(kBT),
-                     0, s, part, L.nparam, grad);
+  hipLaunchKernelGGL(bwd_reduce_kernel,
+                     dim3((unsigned)((L.nparam + kReduceThreads - 1) / kReduceThreads)),
+                     dim3(kReduceThreads), 0, s, part, L.nparam, grad);
   return launch_check("bwd_reduce_kernel");
 }
 
