@@ -218,24 +218,57 @@ __global__ __launch_bounds__(kBT) void bwd_head_kernel(
   const int w = blockIdx.x * 4 + wave;
   f32x4 acc[1][4] = {};
   float bsum[NOUT] = {};
+  // One wave per SIMD: the next chunk's inputs (both groups) are loaded while
+  // this chunk is computed; one explicit wait before the chunk's first store
+  // covers them.
+  float g_nx[2][9], G_nx[2][9], z_nx[2][NOUT], tau_nx[2];
+  u32x4 hf_nx[2][2];
+  auto prefetch = [&](long long cc) {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const Pos P = group_pos(2 * cc + hh, ngroups, n, nx, ny, gxn);
+      const size_t lat = (size_t)P.b * ny * 9 * nx;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        g_nx[hh][i] = gpre[lat + lbm::pidx(nx, P.y, i, P.x)];
+        G_nx[hh][i] = G[lat + lbm::pidx(nx, P.y, i, P.x)];
+      }
+#pragma unroll
+      for (int k = 0; k < NOUT; ++k) z_nx[hh][k] = save_z[P.node * 12 + k];
+      tau_nx[hh] = tau[P.b];
+      load_frags(hR, P.node, q, hf_nx[hh]);
+    }
+  };
+  if (w < nchunks) prefetch(w);
+  __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
   for (long long c = w; c < nchunks; c += kBwdWaves) {
+    float gc[2][9], Gc[2][9], zc[2][NOUT], tauc[2];
+    u32x4 hfc[2][2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        gc[hh][i] = g_nx[hh][i];
+        Gc[hh][i] = G_nx[hh][i];
+      }
+#pragma unroll
+      for (int k = 0; k < NOUT; ++k) zc[hh][k] = z_nx[hh][k];
+      tauc[hh] = tau_nx[hh];
+      hfc[hh][0] = hf_nx[hh][0];
+      hfc[hh][1] = hf_nx[hh][1];
+    }
+    if (c + kBwdWaves < nchunks) prefetch(c + kBwdWaves);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       Pos P = group_pos(2 * c + half, ngroups, n, nx, ny, gxn);
-      const size_t lat = (size_t)P.b * ny * 9 * nx;
-      float g[9], Gi[9], z[NOUT];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        g[i] = gpre[lat + lbm::pidx(nx, P.y, i, P.x)];
-        Gi[i] = G[lat + lbm::pidx(nx, P.y, i, P.x)];
-      }
-#pragma unroll
-      for (int k = 0; k < NOUT; ++k) z[k] = save_z[P.node * 12 + k];
+      float(&g)[9] = gc[half];
+      float(&Gi)[9] = Gc[half];
+      float(&z)[NOUT] = zc[half];
       float drho, rho, u, v, uu;
       lbm::node_moments(g, drho, rho, u, v, uu);
       const float s = 1.0f / (1.0f + expf(-z[0]));
       const float tadj = 0.5f + s;
-      const float tb = tau[P.b];
+      const float tb = tauc[half];
       float dta = 0.0f, m0 = 0.0f, mx = 0.0f, my = 0.0f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
@@ -266,9 +299,9 @@ __global__ __launch_bounds__(kBT) void bwd_head_kernel(
       f32x4 o[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) o[t] = mfma(wht[t], dzb, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+      if (half == 0) __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
       if (P.valid) store_acc(dh, P.node, q, o);
-      u32x4 hf[2];
-      load_frags(hR, P.node, q, hf);
+      const u32x4 hf[2] = {hfc[half][0], hfc[half][1]};
       const int col = 16 * half + n;
 #pragma unroll
       for (int k = 0; k < NOUT; ++k)
@@ -739,12 +772,17 @@ __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
     float *__restrict__ part) {
   __shared__ Stage<64, 64> st[4];
   __shared__ uint16_t d1s[4][64 * kPitch], x1s[4][16 * kPitch];
+  __shared__ u32x4 w2t_s[8 * 64], w1_s[4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
   Stage<64, 64> &S = st[wave];
   uint16_t *D1 = d1s[wave], *X1 = x1s[wave];
   const u32x4 *frags = (const u32x4 *)(pack + F.frag_off);
   const f32x4 *bias = (const f32x4 *)(pack + F.bias_off);
+  // W2^T and W1 are read from LDS inside the loop, so that the loop issues
+  // no global loads besides its node data
+  for (int k = threadIdx.x; k < 8 * 64; k += kBT) w2t_s[k] = frags[(size_t)F.W2T * 64 + k];
+  for (int k = threadIdx.x; k < 4 * 64; k += kBT) w1_s[k] = frags[(size_t)F.W1 * 64 + k];
   u32x4 w2[4][2];
   f32x4 b1[4], b2[4];
 #pragma unroll
@@ -757,17 +795,32 @@ __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
   const long long gxn = (nx + 15) / 16, ngroups = (long long)batch * ny * gxn;
   const long long nchunks = (ngroups + 1) / 2;
   const int w = blockIdx.x * 4 + wave;
+  __syncthreads();
   f32x4 acc2[4][4] = {}, acc1[4][1] = {};
   f32x4 s1[4] = {}, s2[4] = {};
+  // One wave per SIMD: the next group's first-layer output, features and
+  // incoming gradient are loaded while this group is computed (the loop has
+  // no stores, so the compiler's in-order load counts cover them).
+  u32x4 e1_nx[2], xb_nx;
+  f32x4 G_nx[4];
+  auto prefetch = [&](long long grp) {
+    const Pos P = group_pos(grp, ngroups, n, nx, ny, gxn);
+    load_frags(se1, P.node, q, e1_nx);
+    xb_nx = q < 2 ? ((const u32x4 *)(sx + P.node * 16))[q] : u32x4{0u, 0u, 0u, 0u};
+    load_acc(dh0, P.node, q, G_nx);
+  };
+  if (w < nchunks) prefetch(2 * (long long)w);
   for (long long c = w; c < nchunks; c += kBwdWaves) {
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
+      int wo = lane;
+      asm volatile("" : "+v"(wo));
       Pos P = group_pos(2 * c + half, ngroups, n, nx, ny, gxn);
-      u32x4 e1[2];
-      load_frags(se1, P.node, q, e1);
-      const u32x4 xb = q < 2 ? ((const u32x4 *)(sx + P.node * 16))[q] : u32x4{0u, 0u, 0u, 0u};
-      f32x4 G[4];
-      load_acc(dh0, P.node, q, G);
+      const u32x4 e1[2] = {e1_nx[0], e1_nx[1]};
+      const u32x4 xb = xb_nx;
+      const f32x4 G[4] = {G_nx[0], G_nx[1], G_nx[2], G_nx[3]};
+      if (half == 0 || c + kBwdWaves < nchunks)
+        prefetch(half == 0 ? 2 * c + 1 : 2 * (c + kBwdWaves));
       f32x4 dp2[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -780,10 +833,9 @@ __global__ __launch_bounds__(kBT) void bwd_encoder_kernel(
       f32x4 dp1[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        f32x4 de1 = mfma(load_frag(frags, F.W2T + 2 * t, lane), dpb[0],
-                         f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-        de1 = mfma(load_frag(frags, F.W2T + 2 * t + 1, lane), dpb[1], de1);
-        f32x4 p1 = mfma(load_frag(frags, F.W1 + t, lane), xb, b1[t]);
+        f32x4 de1 = mfma(w2t_s[(2 * t) * 64 + wo], dpb[0], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+        de1 = mfma(w2t_s[(2 * t + 1) * 64 + wo], dpb[1], de1);
+        f32x4 p1 = mfma(w1_s[t * 64 + wo], xb, b1[t]);
         dp1[t] = de1 * act_grad4<ACT>(p1);
         s1[t] += dp1[t];
       }
