@@ -283,16 +283,17 @@ def main(argv=None):
     ap.add_argument("--n-fine", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--s-delta", type=float, default=1e-4)
+    ap.add_argument("--rounds", type=int, default=2, help="2: message passing; 0: Fig. 2")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     cfg = DataConfig(n_fine=args.n_fine, runs=args.runs)
     t0 = time.perf_counter()
-    tr, rep = train(cfg, steps=args.steps, batch=args.batch, lr=args.lr, s_delta=args.s_delta,
-                    log_every=max(1, args.steps // 20))
+    tr, rep = train(cfg, steps=args.steps, batch=args.batch, rounds=args.rounds, lr=args.lr,
+                    s_delta=args.s_delta, log_every=max(1, args.steps // 20))
     torch.cuda.synchronize()
     rep["wall_s"] = time.perf_counter() - t0
     rep["config"] = dataclasses.asdict(cfg)
-    rep["steps"], rep["batch"], rep["lr"] = args.steps, args.batch, args.lr
+    rep["steps"], rep["batch"], rep["lr"], rep["rounds"] = args.steps, args.batch, args.lr, args.rounds
     print(json.dumps(rep), flush=True)
     if args.out:
         tr.save(args.out)
