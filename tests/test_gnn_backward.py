@@ -43,7 +43,10 @@ def _gpu_grad(g_planes, G_planes, taus, blob):
     return grad.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("B,ny,nx,sd", [(2, 12, 20, 1.0), (1, 17, 19, 1e-2), (1, 3, 4, 1.0)])
+# the last two: one-row and one-column lattices, where every neighbour of the
+# staged 3 x 18 ring wraps onto the lattice itself
+@pytest.mark.parametrize("B,ny,nx,sd", [(2, 12, 20, 1.0), (1, 17, 19, 1e-2), (1, 3, 4, 1.0),
+                                        (1, 1, 7, 1.0), (2, 5, 1, 1.0)])
 def test_backward_matches_oracle_gradient(orc, B, ny, nx, sd):
     g = inputs.random_shifted_state((B, 9, ny, nx), 4e-3, seed=100 + nx)
     G = inputs.random_shifted_state((B, 9, ny, nx), 1.0, seed=200 + nx)
@@ -61,6 +64,35 @@ def test_backward_matches_oracle_gradient(orc, B, ny, nx, sd):
     print("per-tensor rel-L2:", {k: f"{v:.1e}" for k, v in worst.items()})
     assert max(worst.values()) <= 2e-2, worst
     assert _rel(got, ref) <= 1e-2
+
+
+def test_backward_is_additive_over_lattices():
+    """The gradient is linear in dL/dg_post and separable over the lattices of
+    a batch: a batch of 8 lattices of 128^2 (four chunks of groups per wave of
+    the backward grid, so every kernel walks several chunks and prefetches the
+    next) equals the sum of the 8 single-lattice gradients (at most one chunk
+    per wave), up to the order of the FP32 sums.  A group skipped or counted
+    twice would miss by orders of magnitude more."""
+    B, n = 8, 128
+    g = _dev(np.stack([inputs.planes_to_rows(inputs.random_shifted_state((9, n, n), 4e-3, seed=s))
+                       for s in range(B)]))
+    G = _dev(np.stack([inputs.planes_to_rows(inputs.random_shifted_state((9, n, n), 1.0, seed=50 + s))
+                       for s in range(B)]))
+    t = _dev(np.float32(0.55 + 0.01 * np.arange(B)))
+    b = _dev(inputs.gnn_blob(12, R, s_delta=1.0))
+
+    def grad_of(gg, GG, tt):
+        saved = torch.empty(gnn.saved_bytes(gg.shape[0], n, n, R), dtype=torch.uint8, device="cuda")
+        gnn.gnn_forward(gg, tt, b, R, saved=saved)
+        return gnn.gnn_backward(GG, gg, saved, tt, b, R).double()
+
+    whole = grad_of(g, G, t)
+    parts = sum(grad_of(g[i:i + 1].contiguous(), G[i:i + 1].contiguous(), t[i:i + 1].contiguous())
+                for i in range(B))
+    torch.cuda.synchronize()
+    rel = float((whole - parts).norm() / parts.norm())
+    print(f"batch gradient vs sum of single-lattice gradients: rel-L2 {rel:.1e}")
+    assert torch.isfinite(whole).all() and rel <= 1e-4
 
 
 def test_backward_is_deterministic():
