@@ -234,7 +234,9 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     for start in ("equilibrium", "slow"):
         for name, b, rr in (("bgk", None, 2), ("gnn", tr.blob, 2), ("fig2_network", tr0.blob, 0)):
             rep_tv = experiments.tgv_validation(b, rounds=rr, start=start)
-            tv[f"{name}_{start}_start"] = [float(f"{r['vel_err']:.4g}") for r in rep_tv["rows"]]
+            tv[f"{name}_{start}_start"] = {
+                "vel_err": [float(f"{r['vel_err']:.4g}") for r in rep_tv["rows"]],
+                "energy_err": [float(f"{r['energy_err']:.4g}") for r in rep_tv["rows"]]}
     out["tgv_validation_64_re100"] = {"steps": [1000, 3000, 5000], **tv}
     # which head moves the rollout error (relaxation time or correction)
     out["head_ablation"] = {"message_passing": experiments.head_ablation(tr.blob, rounds=2),

@@ -406,10 +406,29 @@ def poiseuille_study(re_list=(10, 50, 100, 200), ny=32, u_max=0.05, nx=4,
             "collision": "bgk" if blob is None else "fig2-network", "rows": rows}
 
 
+def poiseuille_refinement(heights=(16, 32, 64), re=100.0, u_max=0.05, fp64=False, blob=None,
+                          diffusion_times=4.0):
+    """Grid refinement of the channel (the validation section's Poiseuille
+    convergence figure): the same flow (Re, u_max) on channels of height H,
+    the largest velocity error of each and the observed order between
+    neighbouring heights, alpha = log(E1 / E2) / log(H2 / H1)."""
+    rows = []
+    for h in heights:
+        r = poiseuille_study(re_list=(re,), ny=h, u_max=u_max, fp64=fp64, blob=blob,
+                             diffusion_times=diffusion_times)["rows"][0]
+        r["ny"] = h
+        rows.append(r)
+    alpha = [round(math.log(a["max_rel_err"] / b["max_rel_err"]) / math.log(b["ny"] / a["ny"]), 3)
+             for a, b in zip(rows, rows[1:])]
+    return {"re": re, "u_max": u_max, "fp64": fp64,
+            "collision": "bgk" if blob is None else "fig2-network", "rows": rows, "alpha": alpha}
+
+
 def main(argv=None):
     """Runs one study and prints its report as JSON:
     python -m paper_2504_14494_amd.experiments {fixed-error, resolution,
-    stability, poiseuille, long-rollout, tgv-validation} [--rounds R].  The corrected-collision
+    stability, poiseuille, poiseuille-refinement, long-rollout, tgv-validation}
+    [--rounds R].  The corrected-collision
     studies first train the network (train.train, full configuration); the
     Poiseuille study runs a network only with --rounds 0 (the per-node
     network has no neighbours across a wall; message passing has no wall
@@ -421,7 +440,7 @@ def main(argv=None):
     from . import train
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["fixed-error", "resolution", "stability", "poiseuille",
-                                      "long-rollout", "tgv-validation"])
+                                      "poiseuille-refinement", "long-rollout", "tgv-validation"])
     ap.add_argument("--rounds", type=int, default=2, help="2: message passing; 0: Fig. 2")
     ap.add_argument("--scaling", default="diffusive", choices=["diffusive", "acoustic"])
     ap.add_argument("--fp64", action="store_true", help="BGK runs in FP64 (resolution, poiseuille)")
@@ -431,7 +450,8 @@ def main(argv=None):
     blob = None
     if args.study in ("fixed-error", "stability", "long-rollout", "tgv-validation") or (
             args.study == "resolution" and not args.fp64) or (
-            args.study == "poiseuille" and args.rounds == 0 and not args.fp64):
+            args.study in ("poiseuille", "poiseuille-refinement") and args.rounds == 0
+            and not args.fp64):
         tr, rep = train.train(train.DataConfig(), steps=2000, batch=32, rounds=args.rounds)
         blob = tr.blob
     if args.study == "fixed-error":
@@ -446,6 +466,10 @@ def main(argv=None):
         out = {"bgk": poiseuille_study(fp64=args.fp64)}
         if blob is not None:
             out["fig2_network"] = poiseuille_study(blob=blob)
+    elif args.study == "poiseuille-refinement":
+        out = {"bgk": poiseuille_refinement(fp64=args.fp64)}
+        if blob is not None:
+            out["fig2_network"] = poiseuille_refinement(blob=blob)
     elif args.study == "tgv-validation":
         out = {f"{name}_{start}_start": tgv_validation(b, rounds=args.rounds, start=start)
                for start in ("equilibrium", "slow") for name, b in (("bgk", None), ("gnn", blob))}

@@ -145,3 +145,16 @@ def test_tgv_validation_bgk_matches_the_oracle(orc):
     got = rep["rows"][0]["vel_err"]
     print(f"velocity error at 1000 steps: GPU {got:.6e}, oracle {err:.6e}")
     assert abs(got - err) <= 1e-5
+
+
+def test_poiseuille_refinement_is_second_order_for_bgk():
+    """Channel refinement at fixed Re: plain BGK's error is the bounce-back
+    slip, (16 (tau - 1/2)^2 - 3) / (3 H^2) of u_max, so the observed order
+    between H = 8 and 16 is close to 2 (tau moves with H at fixed Re, which
+    the closed form includes) and each error matches the closed form."""
+    rep = experiments.poiseuille_refinement(heights=(8, 16), re=20.0, fp64=True,
+                                            diffusion_times=3.0)
+    print(rep["alpha"], [(r["max_rel_err"], r["slip_rel_closed_form"]) for r in rep["rows"]])
+    for r in rep["rows"]:
+        assert abs(r["max_rel_err"] - abs(r["slip_rel_closed_form"])) < 2e-3 * abs(r["slip_rel_closed_form"]) + 1e-7
+    assert 1.8 < rep["alpha"][0] < 2.3
