@@ -598,9 +598,12 @@ __global__ __launch_bounds__(kBT) void bwd_edge_recv_kernel(
         // Unconditional, so the compiler also counts them as complete.
         if (d == 6) __builtin_amdgcn_s_waitcnt(kBwdWaitVmcnt0);
         if (P.valid) {
+          // non-temporal: 1 KB per node, read back once by the sender side
+          // (measured: the sender side then runs 18 % faster, this kernel 4 %
+          // slower)
           u32x4 *o = (u32x4 *)(dq_out + (P.node * 8 + (d - 1)) * HID);
-          o[q] = frag_from_acc(dq[0], dq[1]);
-          o[4 + q] = frag_from_acc(dq[2], dq[3]);
+          __builtin_nontemporal_store(frag_from_acc(dq[0], dq[1]), o + q);
+          __builtin_nontemporal_store(frag_from_acc(dq[2], dq[3]), o + 4 + q);
         }
         if (d < 8) {
           // each of edge d + 1's 12 MFMAs followed by 10 VALU instructions
@@ -686,8 +689,8 @@ __global__ __launch_bounds__(kBT) void bwd_edge_send_kernel(
       yn = yn < 0 ? yn + ny : (yn >= ny ? yn - ny : yn);
       const u32x4 *src =
           (const u32x4 *)(dq_in + ((lat_nodes + (size_t)yn * nx + xn) * 8 + (d - 1)) * HID);
-      dq_nx[d - 1][0] = src[q];
-      dq_nx[d - 1][1] = src[4 + q];
+      dq_nx[d - 1][0] = __builtin_nontemporal_load(src + q);  // read once
+      dq_nx[d - 1][1] = __builtin_nontemporal_load(src + 4 + q);
     }
     load_frags(h, P.node, q, hm_nx);
     load_acc(dh, P.node, q, dh_nx);
