@@ -968,7 +968,7 @@ extern "C" int gnn_backward(const float *dL_dgpost, const float *g_pre, const vo
   const BackwardScratch W = backward_scratch(nodes, R);
   const SavedLayout SL = saved_layout(nodes, R);
   uint8_t *pack = (uint8_t *)at(workspace, W.pack);
-  if (int rc = launch_prep(params, R, pack, s)) return rc;
+  if (int rc = launch_prep(params, R, pack, nullptr, s)) return rc;
   float *part = (float *)at(workspace, W.part);
   float *dh[2] = {(float *)at(workspace, W.dhA), (float *)at(workspace, W.dhB)};
   float *dagg = (float *)at(workspace, W.dagg);

@@ -165,7 +165,7 @@ __device__ __forceinline__ f32x4 load_bias(const f32x4 *__restrict__ bias, int b
 }
 
 // Packs the FP32 blob into `pack` (frag_layout(R).total bytes) on stream s.
-int launch_prep(const float *params, int R, uint8_t *pack, hipStream_t s);
+int launch_prep(const float *params, int R, uint8_t *pack, unsigned *ctrl, hipStream_t s);
 
 // Makes the LDS writes of this wave visible to all of its lanes before the
 // reads that follow (LDS staging private to one wave).
@@ -211,6 +211,76 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ gate ---
+
+// The per-step fallback gate, as seen by the kernel that produces the
+// corrected step's per-workgroup FP64 mass and flag partials.  Control words
+// (in the caller's workspace): ctrl[0] = the step's decision, ctrl[1] =
+// workgroups of the producing kernel done, ctrl[2] = workgroups of the
+// fallback kernel done.  gnn_prep_kernel, which starts every step, zeroes
+// the two counts.  arrive == NULL means the step runs without the gate.
+struct GateArgs {
+  unsigned *ctrl;        // control words above, or NULL (no gate)
+  double threshold;      // relative mass drift allowed per step
+  unsigned *flags;       // OR-ed: 1 = negative / non-finite population, 2 = drift
+  unsigned *n_fallback;  // steps that fell back, or NULL
+  double *mass;          // total mass of the previous state (FP64), in/out
+};
+
+// Called by all kThreads threads of every workgroup of the producing kernel,
+// after its thread 0 stored the workgroup's partials.  The workgroup that
+// finishes last sums every partial in index order (a fixed order: the same
+// decision for the same state) and decides: bit 1 = a negative or non-finite
+// population, bit 2 = relative change of total mass not <= threshold.  A
+// kept step records its new mass here; a tripped one records the flags and
+// the fallback count, and the fallback kernel then writes the mass of what it
+// stored.  sm and sf are shared scratch of kThreads entries each; every
+// thread takes part in the barriers, so no thread may have left before.
+template <int kThreads>
+__device__ void gate_decide_last(const GateArgs &g, const double *pmass, const unsigned *pflag,
+                                 int nparts, double nodes, double *sm, unsigned *sf) {
+  if (threadIdx.x == 0) {
+    __threadfence();  // this workgroup's partials before its arrival
+    const unsigned done = atomicAdd(&g.ctrl[1], 1u);
+    sf[0] = done == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  const bool last = sf[0] != 0u;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // every other workgroup's partials are visible
+  double m = 0.0;
+  unsigned f = 0;
+  for (int k = threadIdx.x; k < nparts; k += kThreads) {
+    m += pmass[k];
+    f |= pflag[k];
+  }
+  sm[threadIdx.x] = m;
+  sf[threadIdx.x] = f;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] += sm[threadIdx.x + s];
+      sf[threadIdx.x] |= sf[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mnew = nodes + sm[0];
+    const double mold = *g.mass;
+    unsigned fl = sf[0] ? 1u : 0u;
+    const double rel = fabs(mnew - mold) / mold;
+    if (!(rel <= g.threshold)) fl |= 2u;
+    g.ctrl[0] = fl;
+    if (fl) {
+      *g.flags |= fl;
+      if (g.n_fallback) *g.n_fallback += 1u;
+    } else {
+      *g.mass = mnew;
+    }
+  }
 }
 
 }  // namespace gnn

@@ -128,8 +128,14 @@ __device__ float bias_value(const float *__restrict__ blob, const BlobLayout &L,
 
 __global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ blob, int R,
                                                       BlobLayout L, FragLayout F,
-                                                      uint8_t *__restrict__ pack) {
+                                                      uint8_t *__restrict__ pack,
+                                                      unsigned *__restrict__ ctrl) {
   int lane = threadIdx.x, f = blockIdx.x;
+  // the fallback gate's arrival counts start every step at zero
+  if (ctrl && f == 0 && lane == 0) {
+    ctrl[1] = 0u;
+    ctrl[2] = 0u;
+  }
   if (f < F.nfrag) {
     u32x4 v;
     uint32_t w[4];
@@ -288,6 +294,7 @@ struct HeadArgs {
   float *save_z;          // [N][12] head outputs kept for the backward pass
   double *pmass;          // [gridDim.x] FP64 sum of g* over the nodes of a workgroup
   unsigned *pflag;        // [gridDim.x] 1 if a population came out negative / non-finite
+  GateArgs gate;          // the fallback gate (gate.ctrl NULL: none)
 };
 
 // Corrected collision of one node (Eq. 3 with the projected correction),
@@ -687,59 +694,27 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       args.pmass[blockIdx.x] = red_m[0];
       args.pflag[blockIdx.x] = red_f[0];
     }
+    if constexpr (PULL) {
+      if (args.gate.ctrl)
+        gate_decide_last<kRoundThreads>(args.gate, args.pmass, args.pflag, (int)gridDim.x,
+                                        (double)batch * nx * ny, red_m, red_f);
+    }
   }
 }
 
 // ------------------------------------------------------------ fallback ---
 
-// Sums the per-workgroup partials of the corrected step in a fixed order and
-// decides whether the step falls back: bit 1 = a negative or non-finite
-// population, bit 2 = relative change of total mass not <= threshold.
-__global__ __launch_bounds__(kThreads) void gate_decide_kernel(
-    const double *__restrict__ pmass, const unsigned *__restrict__ pflag, int nparts,
-    double nodes, double threshold, unsigned *__restrict__ flags,
-    unsigned *__restrict__ n_fallback, double *__restrict__ mass, unsigned *__restrict__ ctrl) {
-  __shared__ double sm[kThreads];
-  __shared__ unsigned sf[kThreads];
-  double m = 0.0;
-  unsigned f = 0;
-  for (int k = threadIdx.x; k < nparts; k += kThreads) {
-    m += pmass[k];
-    f |= pflag[k];
-  }
-  sm[threadIdx.x] = m;
-  sf[threadIdx.x] = f;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      sm[threadIdx.x] += sm[threadIdx.x + s];
-      sf[threadIdx.x] |= sf[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double mnew = nodes + sm[0];
-    double mold = *mass;
-    unsigned fl = sf[0] ? 1u : 0u;
-    double rel = fabs(mnew - mold) / mold;
-    if (!(rel <= threshold)) fl |= 2u;
-    ctrl[0] = fl;
-    if (fl) {
-      *flags |= fl;
-      if (n_fallback) *n_fallback += 1u;
-    } else {
-      *mass = mnew;
-    }
-  }
-}
-
 // Plain BGK step from the unchanged source when the gate tripped (same
 // arithmetic as bgk_pull_kernel, grid-stride; for the channel, the same as
-// channel_pull_kernel: walls and forcing); exits at once otherwise.
+// channel_pull_kernel: walls and forcing); exits at once otherwise.  The
+// workgroup that finishes last sums the FP64 partials of what was stored in
+// index order and records it as the new total mass.
 __global__ __launch_bounds__(kThreads) void gate_fallback_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, float omega,
-    int walls, float gx, const unsigned *__restrict__ ctrl, double *__restrict__ pmass2) {
+    int walls, float gx, unsigned *__restrict__ ctrl, double *__restrict__ pmass2,
+    double *__restrict__ mass) {
   __shared__ double sm[kThreads];
+  __shared__ unsigned last_s;
   if (ctrl[0] == 0) return;
   double m = 0.0;
   const size_t nodes = (size_t)nx * ny;
@@ -767,25 +742,24 @@ __global__ __launch_bounds__(kThreads) void gate_fallback_kernel(
     if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) pmass2[blockIdx.x] = sm[0];
-}
-
-// After a fallback: the mass of the state actually written.
-__global__ __launch_bounds__(kThreads) void gate_mass_kernel(const double *__restrict__ pmass2,
-                                                             int nparts, double nodes,
-                                                             const unsigned *__restrict__ ctrl,
-                                                             double *__restrict__ mass) {
-  __shared__ double sm[kThreads];
-  if (ctrl[0] == 0) return;
-  double m = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += kThreads) m += pmass2[k];
+  if (threadIdx.x == 0) {
+    pmass2[blockIdx.x] = sm[0];
+    __threadfence();  // the partial before the arrival
+    const unsigned done = atomicAdd(&ctrl[2], 1u);
+    last_s = done == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();  // every other workgroup's partial is visible
+  m = 0.0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) m += pmass2[k];
   sm[threadIdx.x] = m;
   __syncthreads();
   for (int s = kThreads / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *mass = nodes + sm[0];
+  if (threadIdx.x == 0) *mass = (double)nodes + sm[0];
 }
 
 }  // namespace gnn
@@ -824,12 +798,12 @@ extern "C" size_t gnn_blob_len(int n_rounds) {
 
 namespace gnn {
 
-int launch_prep(const float *params, int R, uint8_t *pack, hipStream_t s) {
+int launch_prep(const float *params, int R, uint8_t *pack, unsigned *ctrl, hipStream_t s) {
   const BlobLayout L = blob_layout(R);
   const FragLayout F = frag_layout(R);
   if (F.total > kPackBytes) return fail(LBM_EINVAL, "packed weights exceed their scratch");
   hipLaunchKernelGGL(gnn_prep_kernel, dim3(F.nfrag + F.nbias + 1), dim3(64), 0, s, params, R, L,
-                     F, pack);
+                     F, pack, ctrl);
   return launch_check("gnn_prep_kernel");
 }
 
@@ -838,12 +812,13 @@ int launch_prep(const float *params, int R, uint8_t *pack, hipStream_t s) {
 // PULL, else pre-collision); the last round writes dst and the partials.
 int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, int ny,
                    const float *tau_arr, float tau, const float *params, int R, float *head_out,
-                   void *saved, void *ws, hipStream_t s, int &nparts) {
+                   void *saved, void *ws, const lbm_fallback *fb, hipStream_t s) {
   const long long nodes = (long long)batch * nx * ny;
   const FragLayout F = frag_layout(R);
   const ForwardScratch W = forward_scratch(nodes);
   uint8_t *pack = (uint8_t *)at(ws, W.pack);
-  if (int rc = launch_prep(params, R, pack, s)) return rc;
+  unsigned *ctrl = (unsigned *)at(ws, W.ctrl);
+  if (int rc = launch_prep(params, R, pack, ctrl, s)) return rc;
 
   const int cus = device_cus();
   const bool save = saved != nullptr;
@@ -876,7 +851,6 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
   long long cap = (long long)cus * 2;
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   int rb = (int)(ntiles < cap ? ntiles : cap);
-  nparts = rb;
   HeadArgs none{};
   HeadArgs ha{};
   ha.src = src;
@@ -887,6 +861,7 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
   ha.save_z = save ? (float *)at(saved, S.z) : nullptr;
   ha.pmass = (double *)at(ws, W.pmass);
   ha.pflag = (unsigned *)at(ws, W.pflag);
+  if (fb && pull) ha.gate = GateArgs{ctrl, fb->drift_threshold, fb->flags, fb->n_fallback, fb->mass};
   for (int r = 0; r < R; ++r) {
     const bool head = r == R - 1;
     uint16_t *hin = hbuf(r);
@@ -919,25 +894,16 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
 
 namespace gnn {
 
-// The per-step fallback gate after a corrected step whose workgroups left
-// nparts FP64 mass partials and flag words: decide, recompute with plain BGK
-// if tripped (the kernel exits at once otherwise), and update the mass.
+// The fallback kernel of the per-step gate, after a corrected step whose last
+// workgroup took the decision into ctrl[0]: recompute with plain BGK if
+// tripped (the kernel exits at once otherwise) and record the new mass.
 int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau, int walls,
-                float gx, const lbm_fallback *fb, int nparts, void *pmass, void *pflag,
-                void *pmass2, void *ctrl, hipStream_t s) {
-  double nodes = (double)nx * ny;
-  hipLaunchKernelGGL(gate_decide_kernel, dim3(1), dim3(kThreads), 0, s, (const double *)pmass,
-                     (const unsigned *)pflag, nparts, nodes, fb->drift_threshold, fb->flags,
-                     fb->n_fallback, fb->mass, (unsigned *)ctrl);
-  if (int rc = launch_check("gate_decide_kernel")) return rc;
+                float gx, const lbm_fallback *fb, void *pmass2, void *ctrl, hipStream_t s) {
   long long fbn = ((long long)nx * ny + kThreads - 1) / kThreads;
   int fbb = (int)(fbn < kMaxGnnBlocks ? fbn : kMaxGnnBlocks);
   hipLaunchKernelGGL(gate_fallback_kernel, dim3(fbb), dim3(kThreads), 0, s, g_src, g_dst, nx, ny,
-                     1.0f / tau, walls, gx, (const unsigned *)ctrl, (double *)pmass2);
-  if (int rc = launch_check("gate_fallback_kernel")) return rc;
-  hipLaunchKernelGGL(gate_mass_kernel, dim3(1), dim3(kThreads), 0, s, (const double *)pmass2,
-                     fbb, nodes, (const unsigned *)ctrl, fb->mass);
-  return launch_check("gate_mass_kernel");
+                     1.0f / tau, walls, gx, (unsigned *)ctrl, (double *)pmass2, fb->mass);
+  return launch_check("gate_fallback_kernel");
 }
 
 }  // namespace gnn
@@ -968,9 +934,8 @@ extern "C" int gnn_forward(const float *g_pre, float *g_post, int batch, int nx,
   if (saved && saved_bytes < saved_need)
     return fail(LBM_EWORKSPACE, "gnn_forward: saved buffer needs %zu bytes", saved_need);
   if (int rc = check_device()) return rc;
-  int nparts = 0;
   return launch_forward(false, g_pre, g_post, batch, nx, ny, tau, 0.0f, params, n_rounds,
-                        head_out, saved, workspace, (hipStream_t)stream, nparts);
+                        head_out, saved, workspace, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
@@ -989,12 +954,11 @@ extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, fl
     return fail(LBM_EWORKSPACE, "lbm_step_gnn: workspace needs %zu bytes", need);
   if (int rc = check_device()) return rc;
   hipStream_t s = (hipStream_t)stream;
-  int nparts = 0;
   if (int rc = launch_forward(true, g_src, g_dst, 1, nx, ny, nullptr, tau, params, n_rounds,
-                              nullptr, nullptr, workspace, s, nparts))
+                              nullptr, nullptr, workspace, fb, s))
     return rc;
   if (!fb) return LBM_OK;
   const ForwardScratch W = forward_scratch((long long)nx * ny);
-  return launch_gate(g_src, g_dst, nx, ny, tau, 0, 0.0f, fb, nparts, at(workspace, W.pmass),
-                     at(workspace, W.pflag), at(workspace, W.pmass2), at(workspace, W.ctrl), s);
+  return launch_gate(g_src, g_dst, nx, ny, tau, 0, 0.0f, fb, at(workspace, W.pmass2),
+                     at(workspace, W.ctrl), s);
 }

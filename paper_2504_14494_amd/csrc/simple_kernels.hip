@@ -11,8 +11,9 @@
 // Sizes follow the corrected collision's encoder and head: 12 -> 64 -> 64
 // (ReLU) -> 10.  The parameter blob is the zero-round layout:
 //   W1[64][12] b1[64] W2[64][64] b2[64] Wh[10][64] bh[10] | mu[12] sigma[12] s_delta
-// The weight fragments (gnn_prep_kernel) and the fallback gate kernels are
-// shared with the message-passing step; the collision epilogue is this
+// The weight fragments (gnn_prep_kernel), the gate's decision
+// (gate_decide_last) and its fallback kernel are shared with the
+// message-passing step; the collision epilogue is this
 // file's own, with the same arithmetic except the hardware exp2 and
 // reciprocal in the sigmoid and the relaxation rate.
 #include "channel_common.hpp"
@@ -22,7 +23,7 @@
 namespace gnn {
 
 // Shared with gnn_kernels.hip.
-int launch_prep(const float *params, int R, uint8_t *pack, hipStream_t s);
+int launch_prep(const float *params, int R, uint8_t *pack, unsigned *ctrl, hipStream_t s);
 
 namespace simple {
 
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int batch, int nx, int ny,
     const float *__restrict__ tau_arr, float tau_s, float gx, const uint8_t *__restrict__ pack,
     FragLayout F, float *__restrict__ head_out, double *__restrict__ pmass,
-    unsigned *__restrict__ pflag, SimpleSave sv) {
+    unsigned *__restrict__ pflag, SimpleSave sv, GateArgs gate) {
   __shared__ u32x4 w_s[14 * 64];   // W1 (4), W2 (8), Wh (2) fragments
   __shared__ f32x4 b_s[9 * 4];     // b1 (4), b2 (4), bh (1), per channel group
   __shared__ __attribute__((aligned(16))) uint32_t slot_s[kWaves][64 * kSlot];
@@ -307,14 +308,18 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     pmass[blockIdx.x] = red_m[0];
     pflag[blockIdx.x] = red_f[0];
   }
+  if constexpr (PULL) {
+    if (gate.ctrl)
+      gate_decide_last<kThreads>(gate, pmass, pflag, (int)gridDim.x, (double)nx * ny, red_m,
+                                 red_f);
+  }
 }
 
 }  // namespace simple
 
 // Gate kernels of the message-passing step (gnn_kernels.hip).
 int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau, int walls,
-                float gx, const lbm_fallback *fb, int nparts, void *pmass, void *pflag,
-                void *pmass2, void *ctrl, hipStream_t s);
+                float gx, const lbm_fallback *fb, void *pmass2, void *ctrl, hipStream_t s);
 
 }  // namespace gnn
 
@@ -339,20 +344,22 @@ static int simple_device_cus() {
 static int launch_simple(bool pull, bool walls, float gx, const float *src, float *dst,
                          int batch, int nx, int ny, const float *tau_arr, float tau,
                          const float *params, float *head_out, void *saved, void *ws,
-                         hipStream_t s, int &nparts) {
+                         const lbm_fallback *fb, hipStream_t s) {
   const FragLayout F = frag_layout(0);
   const SimpleScratch W = simple_scratch();
   uint8_t *pack = (uint8_t *)at_(ws, W.pack);
-  if (int rc = launch_prep(params, 0, pack, s)) return rc;
+  unsigned *ctrl = (unsigned *)at_(ws, W.ctrl);
+  if (int rc = launch_prep(params, 0, pack, ctrl, s)) return rc;
   const long long chunks = (long long)batch * ny * ((nx + 63) / 64);
   long long blocks = (chunks + simple::kWaves - 1) / simple::kWaves;
   // exactly the resident blocks: the grid-stride loop then ends evenly
   long long cap = (long long)simple_device_cus() * simple::kBlocksPerCu;
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   const int nb = (int)(blocks < cap ? blocks : cap);
-  nparts = nb;
   double *pm = (double *)at_(ws, W.pmass);
   unsigned *pf = (unsigned *)at_(ws, W.pflag);
+  GateArgs gate{};
+  if (fb && pull) gate = GateArgs{ctrl, fb->drift_threshold, fb->flags, fb->n_fallback, fb->mass};
   simple::SimpleSave sv{};
   if (saved) {
     const SavedLayout SL = saved_layout((long long)batch * nx * ny, 0);
@@ -364,19 +371,19 @@ static int launch_simple(bool pull, bool walls, float gx, const float *src, floa
   if (pull && walls)
     hipLaunchKernelGGL((simple::simple_step_kernel<true, false, true>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, gx,
-                       pack, F, head_out, pm, pf, sv);
+                       pack, F, head_out, pm, pf, sv, gate);
   else if (pull)
     hipLaunchKernelGGL((simple::simple_step_kernel<true, false, false>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
-                       pack, F, head_out, pm, pf, sv);
+                       pack, F, head_out, pm, pf, sv, gate);
   else if (saved)
     hipLaunchKernelGGL((simple::simple_step_kernel<false, true, false>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
-                       pack, F, head_out, pm, pf, sv);
+                       pack, F, head_out, pm, pf, sv, gate);
   else
     hipLaunchKernelGGL((simple::simple_step_kernel<false, false, false>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
-                       pack, F, head_out, pm, pf, sv);
+                       pack, F, head_out, pm, pf, sv, gate);
   return launch_check("simple_step_kernel");
 }
 
@@ -402,10 +409,8 @@ extern "C" int simple_forward(const float *g_pre, float *g_post, int batch, int 
   if (saved && saved_bytes < saved_need)
     return fail(LBM_EWORKSPACE, "simple_forward: saved buffer needs %zu bytes", saved_need);
   if (int rc = check_device()) return rc;
-  int nparts = 0;
   return launch_simple(false, false, 0.0f, g_pre, g_post, batch, nx, ny, tau, 0.0f, params,
-                       head_out, saved,
-                       workspace, (hipStream_t)stream, nparts);
+                       head_out, saved, workspace, nullptr, (hipStream_t)stream);
 }
 
 // The fused step, periodic (walls = 0) or the channel (walls = 1, force gx).
@@ -425,14 +430,12 @@ static int step_simple(const char *who, const float *g_src, float *g_dst, int nx
     return fail(LBM_EWORKSPACE, "%s: workspace needs %zu bytes", who, simple_scratch().total);
   if (int rc = check_device()) return rc;
   hipStream_t s = (hipStream_t)stream;
-  int nparts = 0;
   if (int rc = launch_simple(true, walls, gx, g_src, g_dst, 1, nx, ny, nullptr, tau, params,
-                             nullptr, nullptr, workspace, s, nparts))
+                             nullptr, nullptr, workspace, fb, s))
     return rc;
   if (!fb) return LBM_OK;
   const SimpleScratch W = simple_scratch();
-  return launch_gate(g_src, g_dst, nx, ny, tau, walls ? 1 : 0, gx, fb, nparts,
-                     at_(workspace, W.pmass), at_(workspace, W.pflag), at_(workspace, W.pmass2),
+  return launch_gate(g_src, g_dst, nx, ny, tau, walls ? 1 : 0, gx, fb, at_(workspace, W.pmass2),
                      at_(workspace, W.ctrl), s);
 }
 
