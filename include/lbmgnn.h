@@ -10,8 +10,11 @@
  *  - Every array argument is a DEVICE pointer owned by the caller.  The
  *    library allocates no device memory; scratch space is passed in as
  *    `workspace` (size from lbm_workspace_bytes) and holds nothing between
- *    calls.  Host pointers appear only for small structs (lbm_tgv,
- *    lbm_fallback), which are read during the call.
+ *    calls.  Calls whose work may run at the same time (other streams) need
+ *    workspaces of their own: a call keeps partial sums and the fallback
+ *    gate's counters there while its kernels run.  Host pointers appear only
+ *    for small structs (lbm_tgv, lbm_fallback), which are read during the
+ *    call.
  *  - Populations are stored shifted, g_i = f_i - w_i, as row-interleaved
  *    structure of arrays g[y][i][x]: lattice row y holds nine contiguous runs
  *    of nx values, one per direction i = 0..8 (x fastest; element
