@@ -234,6 +234,55 @@ def test_fallback_on_non_finite_source(orc):
     assert torch.equal(torch.nan_to_num(dst, nan=7.0), torch.nan_to_num(ref, nan=7.0))
 
 
+@pytest.mark.parametrize("net", ["message_passing", "fig2"])
+def test_gate_over_many_workgroups_step_after_step(orc, net):
+    """The gate on a 384 x 512 lattice, where the corrected step runs 512
+    workgroups and the fallback 768, for three steps in a row: kept, forced
+    to fall back (negative threshold), kept.  Each step's decision is taken
+    by whichever workgroup finishes last, found by counting arrivals, so the
+    counts must start from zero at every step.  After each step the recorded
+    mass equals the sum of what was stored (in the kernel's order of
+    summation), the flags and the fallback count are those of the steps so
+    far, and the fallback step's output is the plain BGK step's value for
+    value."""
+    ny, nx = 384, 512
+    post = inputs.random_shifted_state((9, ny, nx), 3e-3, seed=41)
+    a = _dev(inputs.planes_to_rows(post))
+    b = torch.empty_like(a)
+    w = _w(orc)
+    if net == "fig2":
+        blob = _dev(inputs.gnn_blob(12, 0, s_delta=1e-4))
+        step = lambda s, d, fb: gnn.lbm_step_simple(s, d, 0.7, blob, fallback=fb)
+    else:
+        blob = _dev(inputs.gnn_blob(11, R, s_delta=1e-4))
+        step = lambda s, d, fb: gnn.lbm_step_gnn(s, d, 0.7, blob, R, fallback=fb)
+    fb = gnn.Fallback(float((post.astype(np.float64) + w).sum()), 1e-6)
+    ref = torch.empty_like(a)
+    for k, thr in enumerate((1e-6, -1.0, 1e-6)):
+        fb.threshold = thr
+        step(a, b, fb)
+        lbm.lbm_step_bgk(a, ref, 0.7)
+        torch.cuda.synchronize()
+        g = inputs.rows_to_planes(b.cpu().numpy())
+        if net == "fig2" and thr > 0:
+            # the fused step adds each node's nine stored values in FP32
+            # (in direction order) before its FP64 partial sum
+            node = np.zeros(g.shape[1:], np.float32)
+            for i in range(9):
+                node = (node + g[i]).astype(np.float32)
+            expect = ny * nx + node.astype(np.float64).sum()
+        else:
+            expect = ny * nx + g.astype(np.float64).sum()
+        assert abs(fb.mass.item() - expect) / expect < 1e-12, k
+        assert int(fb.n_fallback.item()) == (0 if k == 0 else 1), k
+        assert int(fb.flags.item()) == (0 if k == 0 else 2), k
+        if thr < 0:
+            assert torch.equal(b, ref)
+        else:
+            assert not torch.equal(b, ref)
+        a, b = b, a
+
+
 # ------------------------------------------------------ full-size sample ---
 
 def test_inference_workload_2048_sampled_nodes(orc):
