@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
 
 }  // namespace simple
 
-// Gate kernels of the message-passing step (gnn_kernels.hip).
+// The gate's fallback kernel, shared with the message-passing step (gnn_kernels.hip).
 int launch_gate(const float *g_src, float *g_dst, int nx, int ny, float tau, int walls,
                 float gx, const lbm_fallback *fb, void *pmass2, void *ctrl, hipStream_t s);
 
