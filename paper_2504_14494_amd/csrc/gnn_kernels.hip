@@ -35,71 +35,73 @@ using lbm::cy;
 
 // One thread per (fragment, lane): 8 BF16 A-operand values (or, for bias
 // fragments, 4 FP32 accumulator-layout values).  See gnn_common.hpp for the
-// fragment conventions.
-__device__ float frag_value(const float *__restrict__ blob, const BlobLayout &L,
-                            const FragLayout &F, int R, int f, int lane, int j) {
+// fragment conventions.  The index functions give the blob position of a
+// value, or -1 for the zero padding, so that a thread can issue all of its
+// loads before it waits for any.
+__device__ __forceinline__ long long frag_index(const BlobLayout &L, const FragLayout &F, int R,
+                                                int f, int lane, int j) {
   int m = lane & 15, q = lane >> 4;
   if (f >= F.W1 && f < F.W1 + 4) {
     int t = f - F.W1, k = 8 * q + j;
-    return k < NFEAT ? blob[L.W1 + (size_t)(16 * t + m) * NFEAT + k] : 0.0f;
+    return k < NFEAT ? (long long)(L.W1 + (size_t)(16 * t + m) * NFEAT + k) : -1LL;
   }
   if (f >= F.W2 && f < F.W2 + 8) {
     int t = (f - F.W2) >> 1, s = (f - F.W2) & 1;
-    return blob[L.W2 + (size_t)(16 * t + m) * HID + frag_channel(s, q, j)];
+    return (long long)(L.W2 + (size_t)(16 * t + m) * HID + frag_channel(s, q, j));
   }
   if (f >= F.WH && f < F.WH + 2) {
     int s = f - F.WH;
-    return m < NOUT ? blob[L.Wh + (size_t)m * HID + frag_channel(s, q, j)] : 0.0f;
+    return m < NOUT ? (long long)(L.Wh + (size_t)m * HID + frag_channel(s, q, j)) : -1LL;
   }
   if (f >= F.W2T && f < F.W2T + 8) {  // rows: e1 channels, k: h0 channels
     int t = (f - F.W2T) >> 1, s = (f - F.W2T) & 1;
-    return blob[L.W2 + (size_t)frag_channel(s, q, j) * HID + 16 * t + m];
+    return (long long)(L.W2 + (size_t)frag_channel(s, q, j) * HID + 16 * t + m);
   }
   if (f >= F.WHT && f < F.WHT + 4) {  // rows: h_R channels, k: head outputs
     int t = f - F.WHT, k = 8 * q + j;
-    return k < NOUT ? blob[L.Wh + (size_t)k * HID + 16 * t + m] : 0.0f;
+    return k < NOUT ? (long long)(L.Wh + (size_t)k * HID + 16 * t + m) : -1LL;
   }
   for (int r = 0; r < R; ++r) {
     const size_t We = L.We[r], Wn = L.Wn[r];
     if (f >= F.WA[r] && f < F.WA[r] + 8) {
       int t = (f - F.WA[r]) >> 1, s = (f - F.WA[r]) & 1;
-      return blob[We + (size_t)(16 * t + m) * EDGE_IN + frag_channel(s, q, j)];
+      return (long long)(We + (size_t)(16 * t + m) * EDGE_IN + frag_channel(s, q, j));
     }
     if (f >= F.WB[r] && f < F.WB[r] + 8) {
       int t = (f - F.WB[r]) >> 1, s = (f - F.WB[r]) & 1;
-      return blob[We + (size_t)(16 * t + m) * EDGE_IN + HID + frag_channel(s, q, j)];
+      return (long long)(We + (size_t)(16 * t + m) * EDGE_IN + HID + frag_channel(s, q, j));
     }
     if (f >= F.WC[r] && f < F.WC[r] + 4) {
       int t = f - F.WC[r];
-      return (q == 0 && j < 2) ? blob[We + (size_t)(16 * t + m) * EDGE_IN + 2 * HID + j] : 0.0f;
+      return (q == 0 && j < 2) ? (long long)(We + (size_t)(16 * t + m) * EDGE_IN + 2 * HID + j) : -1LL;
     }
     if (f >= F.WN[r] && f < F.WN[r] + 16) {
       int t = (f - F.WN[r]) >> 2, s = (f - F.WN[r]) & 3;
       int c = s < 2 ? frag_channel(s, q, j) : HID + frag_channel(s - 2, q, j);
-      return blob[Wn + (size_t)(16 * t + m) * NODE_IN + c];
+      return (long long)(Wn + (size_t)(16 * t + m) * NODE_IN + c);
     }
     if (f >= F.WAT[r] && f < F.WAT[r] + 8) {
       int t = (f - F.WAT[r]) >> 1, s = (f - F.WAT[r]) & 1;
-      return blob[We + (size_t)frag_channel(s, q, j) * EDGE_IN + 16 * t + m];
+      return (long long)(We + (size_t)frag_channel(s, q, j) * EDGE_IN + 16 * t + m);
     }
     if (f >= F.WBT[r] && f < F.WBT[r] + 8) {
       int t = (f - F.WBT[r]) >> 1, s = (f - F.WBT[r]) & 1;
-      return blob[We + (size_t)frag_channel(s, q, j) * EDGE_IN + HID + 16 * t + m];
+      return (long long)(We + (size_t)frag_channel(s, q, j) * EDGE_IN + HID + 16 * t + m);
     }
     if (f >= F.WNT[r] && f < F.WNT[r] + 16) {  // 8 row tiles (h then a) x 2 k-steps
       int t = (f - F.WNT[r]) >> 1, s = (f - F.WNT[r]) & 1;
-      return blob[Wn + (size_t)frag_channel(s, q, j) * NODE_IN + 16 * t + m];
+      return (long long)(Wn + (size_t)frag_channel(s, q, j) * NODE_IN + 16 * t + m);
     }
   }
-  return 0.0f;
+  return -1LL;
 }
 
-__device__ float bias_value(const float *__restrict__ blob, const BlobLayout &L,
-                            const FragLayout &F, int R, int b, int lane, int e) {
+__device__ __forceinline__ long long bias_index(const BlobLayout &L, const FragLayout &F, int R,
+                                                int b, int lane, int e) {
   int q = lane >> 4;
   if (b == F.BH) {
     int k = 4 * q + e;
-    return k < NOUT ? blob[L.bh + k] : 0.0f;
+    return k < NOUT ? (long long)(L.bh + k) : -1LL;
   }
   int t, base;
   if (b >= F.B1 && b < F.B1 + 4) {
@@ -121,9 +123,9 @@ __device__ float bias_value(const float *__restrict__ blob, const BlobLayout &L,
         base = (int)L.bn[r];
       }
     }
-    if (base < 0) return 0.0f;
+    if (base < 0) return -1LL;
   }
-  return blob[base + 16 * t + 4 * q + e];
+  return (long long)(base + 16 * t + 4 * q + e);
 }
 
 __global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ blob, int R,
@@ -137,21 +139,37 @@ __global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ 
     ctrl[2] = 0u;
   }
   if (f < F.nfrag) {
+    long long ix[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ix[j] = frag_index(L, F, R, f, lane, j);
+    float x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {  // padding loads blob[0] and discards it
+      const float val = blob[ix[j] >= 0 ? ix[j] : 0];
+      x[j] = ix[j] >= 0 ? val : 0.0f;
+    }
     u32x4 v;
     uint32_t w[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      w[k] = pack_bf16(frag_value(blob, L, F, R, f, lane, 2 * k),
-                       frag_value(blob, L, F, R, f, lane, 2 * k + 1));
+    for (int k = 0; k < 4; ++k) w[k] = pack_bf16(x[2 * k], x[2 * k + 1]);
     v = u32x4{w[0], w[1], w[2], w[3]};
     ((u32x4 *)(pack + F.frag_off))[(size_t)f * 64 + lane] = v;
   } else if (f < F.nfrag + F.nbias) {
     int b = f - F.nfrag;
+    long long ix[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ix[e] = bias_index(L, F, R, b, lane, e);
+    float x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float val = blob[ix[e] >= 0 ? ix[e] : 0];
+      x[e] = ix[e] >= 0 ? val : 0.0f;
+    }
     f32x4 v;
-    v.x = bias_value(blob, L, F, R, b, lane, 0);
-    v.y = bias_value(blob, L, F, R, b, lane, 1);
-    v.z = bias_value(blob, L, F, R, b, lane, 2);
-    v.w = bias_value(blob, L, F, R, b, lane, 3);
+    v.x = x[0];
+    v.y = x[1];
+    v.z = x[2];
+    v.w = x[3];
     ((f32x4 *)(pack + F.bias_off))[(size_t)b * 64 + lane] = v;
   } else if (lane < 25) {
     ((float *)(pack + F.const_off))[lane] = blob[L.mu + lane];
