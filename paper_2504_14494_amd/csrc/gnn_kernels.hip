@@ -38,62 +38,91 @@ using lbm::cy;
 // fragment conventions.  The index functions give the blob position of a
 // value, or -1 for the zero padding, so that a thread can issue all of its
 // loads before it waits for any.
-__device__ __forceinline__ long long frag_index(const BlobLayout &L, const FragLayout &F, int R,
-                                                int f, int lane, int j) {
-  int m = lane & 15, q = lane >> 4;
+
+// Where the 8 values of one lane of fragment f come from: value j sits at
+// base + stride * g(j), with g(j) = frag_channel(s, q, j) (kind 0), 8 q + j
+// while below lim (kind 1), or j for q == 0 and j < 2 (kind 2, the two
+// edge-direction columns); kind 3 is padding only.  The fragment's kind is
+// decoded once per thread: the layout tables are kernel arguments, and
+// walking them for each value made the packing a chain of dependent scalar
+// loads.
+struct FragSrc {
+  long long base;
+  int stride, kind, s, lim;
+};
+
+__host__ __device__ inline FragSrc frag_src(const BlobLayout &L, const FragLayout &F, int R,
+                                            int f, int m) {
+  FragSrc o{0, 1, 3, 0, 0};
   if (f >= F.W1 && f < F.W1 + 4) {
-    int t = f - F.W1, k = 8 * q + j;
-    return k < NFEAT ? (long long)(L.W1 + (size_t)(16 * t + m) * NFEAT + k) : -1LL;
+    o = FragSrc{(long long)(L.W1 + (size_t)(16 * (f - F.W1) + m) * NFEAT), 1, 1, 0, NFEAT};
+  } else if (f >= F.W2 && f < F.W2 + 8) {
+    const int t = (f - F.W2) >> 1, s = (f - F.W2) & 1;
+    o = FragSrc{(long long)(L.W2 + (size_t)(16 * t + m) * HID), 1, 0, s, 0};
+  } else if (f >= F.WH && f < F.WH + 2) {
+    if (m < NOUT) o = FragSrc{(long long)(L.Wh + (size_t)m * HID), 1, 0, f - F.WH, 0};
+  } else if (f >= F.W2T && f < F.W2T + 8) {  // rows: e1 channels, k: h0 channels
+    const int t = (f - F.W2T) >> 1, s = (f - F.W2T) & 1;
+    o = FragSrc{(long long)(L.W2 + 16 * t + m), HID, 0, s, 0};
+  } else if (f >= F.WHT && f < F.WHT + 4) {  // rows: h_R channels, k: head outputs
+    o = FragSrc{(long long)(L.Wh + 16 * (f - F.WHT) + m), HID, 1, 0, NOUT};
+  } else {
+    for (int r = 0; r < R; ++r) {
+      const long long We = (long long)L.We[r], Wn = (long long)L.Wn[r];
+      if (f >= F.WA[r] && f < F.WA[r] + 8) {
+        const int t = (f - F.WA[r]) >> 1, s = (f - F.WA[r]) & 1;
+        o = FragSrc{We + (long long)(16 * t + m) * EDGE_IN, 1, 0, s, 0};
+        break;
+      }
+      if (f >= F.WB[r] && f < F.WB[r] + 8) {
+        const int t = (f - F.WB[r]) >> 1, s = (f - F.WB[r]) & 1;
+        o = FragSrc{We + (long long)(16 * t + m) * EDGE_IN + HID, 1, 0, s, 0};
+        break;
+      }
+      if (f >= F.WC[r] && f < F.WC[r] + 4) {
+        const int t = f - F.WC[r];
+        o = FragSrc{We + (long long)(16 * t + m) * EDGE_IN + 2 * HID, 1, 2, 0, 0};
+        break;
+      }
+      if (f >= F.WN[r] && f < F.WN[r] + 16) {  // k-steps 0, 1: h; 2, 3: aggregate
+        const int t = (f - F.WN[r]) >> 2, s = (f - F.WN[r]) & 3;
+        o = FragSrc{Wn + (long long)(16 * t + m) * NODE_IN + (s < 2 ? 0 : HID), 1, 0, s & 1, 0};
+        break;
+      }
+      if (f >= F.WAT[r] && f < F.WAT[r] + 8) {
+        const int t = (f - F.WAT[r]) >> 1, s = (f - F.WAT[r]) & 1;
+        o = FragSrc{We + 16 * t + m, EDGE_IN, 0, s, 0};
+        break;
+      }
+      if (f >= F.WBT[r] && f < F.WBT[r] + 8) {
+        const int t = (f - F.WBT[r]) >> 1, s = (f - F.WBT[r]) & 1;
+        o = FragSrc{We + HID + 16 * t + m, EDGE_IN, 0, s, 0};
+        break;
+      }
+      if (f >= F.WNT[r] && f < F.WNT[r] + 16) {  // 8 row tiles (h then a) x 2 k-steps
+        const int t = (f - F.WNT[r]) >> 1, s = (f - F.WNT[r]) & 1;
+        o = FragSrc{Wn + 16 * t + m, NODE_IN, 0, s, 0};
+        break;
+      }
+    }
   }
-  if (f >= F.W2 && f < F.W2 + 8) {
-    int t = (f - F.W2) >> 1, s = (f - F.W2) & 1;
-    return (long long)(L.W2 + (size_t)(16 * t + m) * HID + frag_channel(s, q, j));
+  return o;
+}
+
+// Blob position of value j of lane group q, or -1 for padding.
+__host__ __device__ inline long long frag_index(const FragSrc &o, int q, int j) {
+  switch (o.kind) {
+    case 0:
+      return o.base + (long long)o.stride * frag_channel(o.s, q, j);
+    case 1: {
+      const int k = 8 * q + j;
+      return k < o.lim ? o.base + (long long)o.stride * k : -1LL;
+    }
+    case 2:
+      return (q == 0 && j < 2) ? o.base + j : -1LL;
+    default:
+      return -1LL;
   }
-  if (f >= F.WH && f < F.WH + 2) {
-    int s = f - F.WH;
-    return m < NOUT ? (long long)(L.Wh + (size_t)m * HID + frag_channel(s, q, j)) : -1LL;
-  }
-  if (f >= F.W2T && f < F.W2T + 8) {  // rows: e1 channels, k: h0 channels
-    int t = (f - F.W2T) >> 1, s = (f - F.W2T) & 1;
-    return (long long)(L.W2 + (size_t)frag_channel(s, q, j) * HID + 16 * t + m);
-  }
-  if (f >= F.WHT && f < F.WHT + 4) {  // rows: h_R channels, k: head outputs
-    int t = f - F.WHT, k = 8 * q + j;
-    return k < NOUT ? (long long)(L.Wh + (size_t)k * HID + 16 * t + m) : -1LL;
-  }
-  for (int r = 0; r < R; ++r) {
-    const size_t We = L.We[r], Wn = L.Wn[r];
-    if (f >= F.WA[r] && f < F.WA[r] + 8) {
-      int t = (f - F.WA[r]) >> 1, s = (f - F.WA[r]) & 1;
-      return (long long)(We + (size_t)(16 * t + m) * EDGE_IN + frag_channel(s, q, j));
-    }
-    if (f >= F.WB[r] && f < F.WB[r] + 8) {
-      int t = (f - F.WB[r]) >> 1, s = (f - F.WB[r]) & 1;
-      return (long long)(We + (size_t)(16 * t + m) * EDGE_IN + HID + frag_channel(s, q, j));
-    }
-    if (f >= F.WC[r] && f < F.WC[r] + 4) {
-      int t = f - F.WC[r];
-      return (q == 0 && j < 2) ? (long long)(We + (size_t)(16 * t + m) * EDGE_IN + 2 * HID + j) : -1LL;
-    }
-    if (f >= F.WN[r] && f < F.WN[r] + 16) {
-      int t = (f - F.WN[r]) >> 2, s = (f - F.WN[r]) & 3;
-      int c = s < 2 ? frag_channel(s, q, j) : HID + frag_channel(s - 2, q, j);
-      return (long long)(Wn + (size_t)(16 * t + m) * NODE_IN + c);
-    }
-    if (f >= F.WAT[r] && f < F.WAT[r] + 8) {
-      int t = (f - F.WAT[r]) >> 1, s = (f - F.WAT[r]) & 1;
-      return (long long)(We + (size_t)frag_channel(s, q, j) * EDGE_IN + 16 * t + m);
-    }
-    if (f >= F.WBT[r] && f < F.WBT[r] + 8) {
-      int t = (f - F.WBT[r]) >> 1, s = (f - F.WBT[r]) & 1;
-      return (long long)(We + (size_t)frag_channel(s, q, j) * EDGE_IN + HID + 16 * t + m);
-    }
-    if (f >= F.WNT[r] && f < F.WNT[r] + 16) {  // 8 row tiles (h then a) x 2 k-steps
-      int t = (f - F.WNT[r]) >> 1, s = (f - F.WNT[r]) & 1;
-      return (long long)(Wn + (size_t)frag_channel(s, q, j) * NODE_IN + 16 * t + m);
-    }
-  }
-  return -1LL;
 }
 
 __device__ __forceinline__ long long bias_index(const BlobLayout &L, const FragLayout &F, int R,
@@ -139,9 +168,10 @@ __global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ 
     ctrl[2] = 0u;
   }
   if (f < F.nfrag) {
+    const FragSrc fs = frag_src(L, F, R, f, lane & 15);
     long long ix[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ix[j] = frag_index(L, F, R, f, lane, j);
+    for (int j = 0; j < 8; ++j) ix[j] = frag_index(fs, lane >> 4, j);
     float x[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {  // padding loads blob[0] and discards it
