@@ -105,7 +105,13 @@ typedef struct lbm_tgv {
   double u0, kx, ky, x0, y0, nu, t;
 } lbm_tgv;
 
-/* Macroscopic fields and FP64 observables of a (post-collision) state.
+/* Macroscopic fields and FP64 observables of a (post-collision) state: the
+ * density and velocity moments of Eq. 2 (rho = sum f_i, rho u = sum e_i f_i)
+ * and the quantities the Taylor-Green validation (validation section,
+ * "Taylor-Green Vortex Validation") and the Reynolds-number study measure:
+ * the L2 velocity error against the analytic decaying vortex and the kinetic
+ * energy; plus the global mass and momentum the conservation checks and the
+ * fallback gate use.
  * rho, ux, uy: [ny][nx] FP32 outputs, each may be NULL.
  * sums: NULL or device double[8] receiving
  *   [0] total mass  sum rho          [1] sum rho u_x    [2] sum rho u_y
@@ -233,7 +239,9 @@ int gnn_forward(const float *g_pre, float *g_post, int batch, int nx, int ny,
                 float *head_out, void *saved, size_t saved_bytes,
                 void *workspace, size_t ws_bytes, void *stream);
 
-/* Gradient of a scalar loss with respect to the trainable parameters, given
+/* Backward pass of the training step (Methodology, "Training Methodology":
+ * supervised regression of the corrected collision, loss Eq. 4).
+ * Gradient of a scalar loss with respect to the trainable parameters, given
  * dL_dgpost = dL/d g_post at the output of the forward call that filled
  * `saved` (same g_pre, tau and params): gnn_forward for n_rounds >= 1 (GELU
  * message-passing network), simple_forward for n_rounds = 0 (the per-node

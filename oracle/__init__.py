@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, so IEEE FP64 holds)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
-        cmd = ["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off",
+        cmd = ["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
                "-D_GNU_SOURCE", "-shared", "-fPIC", *_SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
@@ -48,6 +48,7 @@ def lib():
         P = ctypes.POINTER
         d, i, sz = ctypes.c_double, ctypes.c_int, ctypes.c_size_t
         pd, pi = P(ctypes.c_double), P(ctypes.c_int)
+        L.orc_set_threads.argtypes = [i]
         L.orc_lattice.argtypes = [pi, pi, pd]
         L.orc_equilibrium.argtypes = [d, d, d, pd]
         L.orc_moments.argtypes = [pd, i, i, pd, pd, pd]
@@ -107,6 +108,12 @@ def _f64(a) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- lattice ---
+
+def set_threads(n: int) -> None:
+    """Threads the BGK collision and streaming loops may share their nodes
+    among (default 1); results do not depend on it."""
+    lib().orc_set_threads(int(n))
+
 
 def lattice():
     ex = (ctypes.c_int * 9)()

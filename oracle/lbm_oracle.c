@@ -14,11 +14,19 @@
  * the textbook one (Krueger et al., cited in the paper's resolution study).
  *
  * Layout of every population array: f[i][y][x], i = 0..8, x fastest.
- * All routines are single-threaded and unoptimised on purpose.
+ * All routines are unoptimised on purpose and single-threaded by default;
+ * orc_set_threads lets the BGK collision and streaming loops share their
+ * independent nodes among several threads, which changes no result (each
+ * node's arithmetic is the same), for the long reference runs only.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int g_threads = 1;
+
+/* Threads the BGK collision and streaming loops may use (default 1). */
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
 
 /* D2Q9: rest, 4 axis directions, 4 diagonals. */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -115,9 +123,9 @@ void orc_init_equilibrium(double *f, int nx, int ny, const double *rho,
 void orc_collide_bgk(const double *f, double *out, int nx, int ny,
                      double tau) {
   size_t plane = (size_t)nx * ny;
-  double feq[9];
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
   for (size_t n = 0; n < plane; ++n) {
-    double rho, ux, uy;
+    double rho, ux, uy, feq[9];
     node_moments(f, plane, n, &rho, &ux, &uy);
     orc_equilibrium(rho, ux, uy, feq);
     for (int i = 0; i < 9; ++i) {
@@ -132,6 +140,7 @@ void orc_collide_bgk(const double *f, double *out, int nx, int ny,
 void orc_stream(const double *in, double *out, int nx, int ny) {
   size_t plane = (size_t)nx * ny;
   for (int i = 0; i < 9; ++i)
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int xd = wrap(x + EX[i], nx), yd = wrap(y + EY[i], ny);

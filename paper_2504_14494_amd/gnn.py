@@ -233,6 +233,14 @@ class GnnLattice(Lattice):
         return super()._graph_buffers() + [self.blob, self.ws.buf, fb.flags, fb.n_fallback,
                                            fb.mass]
 
+    def _graph_key(self, gate: bool):
+        """What a captured corrected step freezes besides the step's own
+        arguments: the parameter blob's address, the number of rounds and,
+        with the gate, the drift threshold (copied into the kernel arguments
+        at capture).  Changing any of them selects another graph."""
+        return (self.blob.data_ptr(), int(self.rounds),
+                float(self.fallback.threshold) if gate else None)
+
     def step_bgk(self, tau: float, n: int = 1, graph: bool = False):
         super().step_bgk(tau, n, graph)
         if n:
@@ -259,8 +267,8 @@ class GnnLattice(Lattice):
                 tmp = Fallback(0.0, self.fallback.threshold)
                 tmp.mass.copy_(self.fallback.mass)
             step(self.a.clone(), torch.empty_like(self.a), tmp)
-        return self._run(("gnn", float(tau), bool(gate)), lambda s, d: step(s, d, fb), warm, n,
-                         graph)
+        return self._run(("gnn", float(tau), bool(gate)) + self._graph_key(gate),
+                         lambda s, d: step(s, d, fb), warm, n, graph)
 
     def step_gnn_channel(self, tau: float, gx: float, n: int = 1, gate: bool = True,
                          graph: bool = False):
@@ -281,7 +289,7 @@ class GnnLattice(Lattice):
                 tmp = Fallback(0.0, self.fallback.threshold)
                 tmp.mass.copy_(self.fallback.mass)
             step(self.a.clone(), torch.empty_like(self.a), tmp)
-        return self._run(("gnn_channel", float(tau), float(gx), bool(gate)),
+        return self._run(("gnn_channel", float(tau), float(gx), bool(gate)) + self._graph_key(gate),
                          lambda s, d: step(s, d, fb), warm, n, graph)
 
 

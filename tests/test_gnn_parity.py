@@ -9,6 +9,9 @@ compared with the oracle in two modes:
   mode 1  FP64 arithmetic with BF16 rounding at the points where the kernel
           stores BF16 (weights, features, activations, summed messages):
           head outputs agree to summation-order effects only.
+Every comparison is made twice: as a relative L2 norm over the field and
+node by node (largest deviation at any node relative to the largest
+reference value), so that a single wrong node fails.
 Layouts: the library stores [.., ny, 9, nx]; the oracle [.., 9, ny, nx]
 (inputs.planes_to_rows / rows_to_planes, a transpose).
 """
@@ -33,6 +36,26 @@ def _dev(a, dtype=torch.float32):
 
 def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _node_max(a, b):
+    """Largest deviation at any node and component, relative to the largest
+    reference value: one wrong node is enough to fail it."""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _head_nodes_ok(z, zref):
+    """Head outputs node by node against the BF16-emulating oracle.  The two
+    sides sum in different orders (FP32 MFMA against FP64), so now and then
+    a value that sits within ~1e-7 of a BF16 rounding boundary rounds the
+    other way; about 5000 rounded values feed each node's head, so some nodes
+    carry one such flip, worth up to ~2e-3 of max|z|.  Bar: within 1e-3 of
+    max|z| at 95 % of the nodes or more, within 5e-3 at every node (a
+    wrong node, e.g. one message missing, is off by several percent)."""
+    dz = np.abs(z - zref).max(axis=-1) / np.abs(zref).max()
+    frac = float(np.mean(dz > 1e-3))
+    print(f"head outputs: worst node {dz.max():.2e} of max|z|, nodes above 1e-3: {frac:.1%}")
+    return dz.max() <= 5e-3 and frac <= 0.05
 
 
 def _forward(g_planes, taus, blob, want_z=True):
@@ -64,9 +87,12 @@ def test_forward_matches_oracle_at_inference_scale(orc, B, ny, nx):
     rel = _rel(got_f, ref)
     bgk = _bgk_planes(orc, f, taus.astype(np.float64))
     rel_corr = _rel(got_f - bgk, ref - bgk)
-    print(f"f* rel-L2 {rel:.2e}; correction rel-L2 {rel_corr:.2e}; z rel {_rel(z, zref):.2e}")
+    node_corr = _node_max(got_f - bgk, ref - bgk)
+    print(f"f* rel-L2 {rel:.2e}; correction rel-L2 {rel_corr:.2e}, per node {node_corr:.2e}; "
+          f"z rel {_rel(z, zref):.2e}")
     assert rel <= 1e-3
     assert rel_corr <= 5e-2
+    assert node_corr <= 5e-2
     assert np.isfinite(got).all()
 
 
@@ -81,9 +107,10 @@ def test_head_matches_bf16_emulating_oracle(orc, B, ny, nx):
     ref1, z1 = orc.gnn_collide(f, taus.astype(np.float64), blob.astype(np.float64), R, mode=1,
                                want_z=True)
     rz, rf = _rel(z, z1), _rel(got + _w(orc), ref1)
-    print(f"vs BF16-emulating oracle: z rel-L2 {rz:.2e}, f* rel-L2 {rf:.2e}")
-    assert rz <= 2e-3
-    assert rf <= 2e-3
+    print(f"vs BF16-emulating oracle: z rel-L2 {rz:.2e}; f* rel-L2 {rf:.2e}")
+    assert rz <= 1e-3
+    assert _head_nodes_ok(z, z1)
+    assert rf <= 1e-3
 
 
 def test_step_gnn_pulls_then_collides(orc):
@@ -101,6 +128,7 @@ def test_step_gnn_pulls_then_collides(orc):
     assert _rel(got, ref) <= 1e-3
     bgk = orc.collide_bgk(fpre, float(tau))
     assert _rel(got - bgk, ref - bgk) <= 5e-2
+    assert _node_max(got - bgk, ref - bgk) <= 5e-2
 
 
 def _zero_head(blob):
@@ -314,6 +342,9 @@ def test_inference_workload_2048_sampled_nodes(orc):
     bgk = np.stack([orc.collide_bgk(fpre[:, y:y + 1, x:x + 1], tau)[:, 0, 0]
                     for y, x in zip(ys, xs)])
     rel_c = _rel(got - bgk, ref - bgk)
-    print(f"2048^2 sampled: f* rel-L2 {rel:.2e}, correction rel-L2 {rel_c:.2e}")
+    node_c = _node_max(got - bgk, ref - bgk)
+    print(f"2048^2 sampled: f* rel-L2 {rel:.2e}, correction rel-L2 {rel_c:.2e}, "
+          f"per node {node_c:.2e}")
     assert rel <= 1e-3
     assert rel_c <= 5e-2
+    assert node_c <= 5e-2

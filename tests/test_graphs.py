@@ -123,3 +123,31 @@ def test_graph_keeps_its_buffers_when_the_workspace_grows():
         g.step_gnn(0.66, CH + 3, graph=True)
         torch.cuda.synchronize()
         assert torch.equal(e.a, g.a)
+
+
+@pytest.mark.parametrize("rounds", [2, 0])
+def test_changing_threshold_or_blob_after_a_graph_run_is_honoured(rounds):
+    """A captured step freezes the drift threshold and the parameter blob's
+    address; after either changes, graph steps must follow the new values
+    (another graph), exactly as eager steps do: same states, same fallback
+    counts, and with a negative threshold every step of the chunk falls
+    back."""
+    blob = torch.as_tensor(inputs.gnn_blob(7, rounds, s_delta=1e-4), device="cuda")
+    other = torch.as_tensor(inputs.gnn_blob(8, rounds, s_delta=1e-4), device="cuda")
+    e, g = _twins(lambda: gnn.GnnLattice(32, 24, blob, rounds).init(*inputs.tgv_velocity(
+        32, 24, 0.04, dtype=np.float32)))
+    step = lambda lat, n, gr: lat.step_gnn(0.64, n, graph=gr)
+    _check_replays(e, g, step, rounds=1, extra=0)
+    assert torch.equal(e.n_fallback, g.n_fallback)
+    before = int(g.n_fallback.item())
+    for lat in (e, g):                      # every step now falls back (drift branch)
+        lat.fallback.threshold = -1.0
+    _check_replays(e, g, step, rounds=1, extra=0)
+    assert torch.equal(e.n_fallback, g.n_fallback)
+    assert int(g.n_fallback.item()) == before + CH
+    for lat in (e, g):
+        lat.fallback.threshold = 1e-6
+        lat.blob = other
+    _check_replays(e, g, step, rounds=1, extra=0)
+    assert torch.equal(e.n_fallback, g.n_fallback)
+    assert torch.equal(e.fallback.mass, g.fallback.mass)

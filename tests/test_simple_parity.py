@@ -5,8 +5,10 @@ fused into the pull step, against the CPU oracle (zero rounds, ReLU).
 
 Same bars as the message-passing collision: corrected populations within
 1e-3 relative of the FP64 oracle at the inference correction scale, the
-correction itself within 5e-2, and head outputs within 2e-3 of the
-BF16-emulating oracle.
+correction itself within 5e-2 (as a relative L2 norm and at every node,
+relative to the largest correction), and head outputs within 1e-3 of the
+BF16-emulating oracle (relative L2, and node by node up to rare BF16
+rounding flips).
 """
 import numpy as np
 import pytest
@@ -29,6 +31,26 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
+def _node_max(a, b):
+    """Largest deviation at any node and component, relative to the largest
+    reference value: one wrong node is enough to fail it."""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _head_nodes_ok(z, zref):
+    """Head outputs node by node against the BF16-emulating oracle.  The two
+    sides sum in different orders (FP32 MFMA against FP64), so now and then
+    a value that sits within ~1e-7 of a BF16 rounding boundary rounds the
+    other way; about 5000 rounded values feed each node's head, so some nodes
+    carry one such flip, worth up to ~2e-3 of max|z|.  Bar: within 1e-3 of
+    max|z| at 95 % of the nodes or more, within 5e-3 at every node (a
+    wrong node, e.g. one message missing, is off by several percent)."""
+    dz = np.abs(z - zref).max(axis=-1) / np.abs(zref).max()
+    frac = float(np.mean(dz > 1e-3))
+    print(f"head outputs: worst node {dz.max():.2e} of max|z|, nodes above 1e-3: {frac:.1%}")
+    return dz.max() <= 5e-3 and frac <= 0.05
+
+
 def _blob(seed, s_delta):
     return inputs.gnn_blob(seed, 0, s_delta=s_delta)
 
@@ -45,8 +67,9 @@ def test_forward_matches_oracle(orc, B, ny, nx):
     ref = orc.gnn_collide(f, taus.astype(np.float64), blob.astype(np.float64), 0, mode=0, act=1)
     bgk = np.stack([orc.collide_bgk(f[b], float(taus[b])) for b in range(B)])
     rel, rel_c = _rel(got, ref), _rel(got - bgk, ref - bgk)
-    print(f"f* rel-L2 {rel:.2e}, correction rel-L2 {rel_c:.2e}")
-    assert rel <= 1e-3 and rel_c <= 5e-2
+    node_c = _node_max(got - bgk, ref - bgk)
+    print(f"f* rel-L2 {rel:.2e}, correction rel-L2 {rel_c:.2e}, per node {node_c:.2e}")
+    assert rel <= 1e-3 and rel_c <= 5e-2 and node_c <= 5e-2
 
 
 @pytest.mark.parametrize("ny,nx", [(6, 70), (16, 64)])
@@ -59,9 +82,11 @@ def test_head_matches_bf16_emulating_oracle(orc, ny, nx):
     ref, zref = orc.gnn_collide(f, np.array([0.8]), blob.astype(np.float64), 0, mode=1, act=1,
                                 want_z=True)
     got = inputs.rows_to_planes(out.double().cpu().numpy()) + _w(orc)
-    rz, rf = _rel(z.double().cpu().numpy(), zref), _rel(got, ref)
-    print(f"vs BF16-emulating oracle: z rel-L2 {rz:.2e}, f* rel-L2 {rf:.2e}")
-    assert rz <= 2e-3 and rf <= 2e-3
+    zg = z.double().cpu().numpy()
+    rz, rf = _rel(zg, zref), _rel(got, ref)
+    print(f"vs BF16-emulating oracle: z rel-L2 {rz:.2e}; f* rel-L2 {rf:.2e}")
+    assert rz <= 1e-3 and rf <= 1e-3
+    assert _head_nodes_ok(zg, zref)
 
 
 def test_fused_step_pulls_then_collides(orc):
@@ -73,8 +98,11 @@ def test_fused_step_pulls_then_collides(orc):
     got = inputs.rows_to_planes(dst.double().cpu().numpy()) + _w(orc)
     fpre = orc.stream(post.astype(np.float64) + _w(orc))
     ref = orc.gnn_collide(fpre, 0.7, blob.astype(np.float64), 0, mode=0, act=1)
+    bgk = orc.collide_bgk(fpre, 0.7)
     assert np.isfinite(got).all()
     assert _rel(got, ref) <= 1e-3
+    assert _rel(got - bgk, ref - bgk) <= 5e-2
+    assert _node_max(got - bgk, ref - bgk) <= 5e-2
 
 
 def test_zero_head_is_the_bgk_step():
@@ -125,7 +153,9 @@ def test_full_size_8192_sampled_rows(orc):
     for y in (0, 1, 4095, 4096, 8190, 8191):
         rows = [(y - 1) % n, y, (y + 1) % n]
         band = inputs.rows_to_planes(src[rows].double().cpu().numpy()) + w
-        ref = orc.gnn_collide(orc.stream(band), 0.7, blob.astype(np.float64), 0, mode=0,
-                              act=1)[:, 1, :]
+        fpre = orc.stream(band)
+        ref = orc.gnn_collide(fpre, 0.7, blob.astype(np.float64), 0, mode=0, act=1)[:, 1, :]
+        bgk = orc.collide_bgk(fpre, 0.7)[:, 1, :]
         got = dst[y].double().cpu().numpy() + w[:, :, 0]
         assert _rel(got, ref) <= 1e-3, y
+        assert _node_max(got - bgk, ref - bgk) <= 5e-2, y
