@@ -227,6 +227,24 @@ int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
                  const float *params, int n_rounds, const lbm_fallback *fb,
                  void *workspace, size_t ws_bytes, void *stream);
 
+/* lbm_step_gnn without a workspace and without any allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The step's scratch
+ * (packed weights, the two node-state buffers, the gate's partials and
+ * counters) lives in a static device array of the library, sized for at most
+ * LBM_NOALLOC_MAX_NODES lattice nodes (about 16.6 MiB); each GPU the library
+ * runs on holds its own copy until the process ends.  The first call on a
+ * device looks up that device's copy; no call allocates or frees memory.
+ * Every call on one GPU shares that GPU's copy: calls that may run at the
+ * same time on one GPU (other streams, other host threads) race and must not
+ * overlap.  Arguments, results and errors are those of lbm_step_gnn; in
+ * addition nx * ny > LBM_NOALLOC_MAX_NODES is rejected with LBM_EINVAL
+ * before anything is enqueued. */
+#define LBM_NOALLOC_MAX_NODES 65536
+int lbm_step_gnn_noalloc(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                         const float *params, int n_rounds, const lbm_fallback *fb,
+                         void *stream);
+
 /* The GNN-corrected collision alone (no streaming) on a batch of
  * independent periodic lattices: g_pre [batch][ny][9][nx] pre-collision,
  * g_post the corrected post-collision state, tau: device float[batch].

@@ -19,13 +19,14 @@ LBM_WS_GNN_SAVED = 3
 LBM_WS_GNN_BACKWARD = 4
 LBM_WS_MSE = 5
 LBM_WS_SIMPLE = 6
+LBM_NOALLOC_MAX_NODES = 65536   # lattice nodes lbm_step_gnn_noalloc's static scratch holds
 
 EXPORTS = [
     "lbm_last_error", "lbm_init", "lbm_init_f64", "lbm_step_bgk", "lbm_step_bgk_f64",
     "lbm_stream", "lbm_init_ce", "lbm_init_ce_f64",
     "lbm_step_channel", "lbm_step_channel_f64", "lbm_channel_profile",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
-    "lbm_step_gnn", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
+    "lbm_step_gnn", "lbm_step_gnn_noalloc", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
     "lbm_step_simple", "lbm_step_simple_channel", "simple_forward", "gnn_gelu_rate",
     "lbm_workspace_bytes",
 ]
@@ -79,6 +80,7 @@ def load(path: str = LIB_PATH):
         "gnn_param_count": ([i], sz),
         "gnn_blob_len": ([i], sz),
         "lbm_step_gnn": ([vp, vp, i, i, f, vp, i, ctypes.POINTER(LbmFallback), vp, sz, vp], i),
+        "lbm_step_gnn_noalloc": ([vp, vp, i, i, f, vp, i, ctypes.POINTER(LbmFallback), vp], i),
         "gnn_forward": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp, sz, vp], i),
         "gnn_backward": ([vp, vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
         "gnn_mse": ([vp, vp, i, i, i, d, vp, vp, vp, sz, vp], i),

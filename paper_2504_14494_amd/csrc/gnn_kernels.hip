@@ -21,6 +21,7 @@
 // MFMA.  All dense layers are BF16 x BF16 -> FP32 MFMA (16x16x32); GELU,
 // the message sum and everything after the head run in FP32 on the VALU.
 #include <cstdio>
+#include <mutex>
 
 #include "channel_common.hpp"
 #include "gnn_common.hpp"
@@ -986,22 +987,10 @@ extern "C" int gnn_forward(const float *g_pre, float *g_post, int batch, int nx,
                         head_out, saved, workspace, nullptr, (hipStream_t)stream);
 }
 
-extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
-                            const float *params, int n_rounds, const lbm_fallback *fb,
-                            void *workspace, size_t ws_bytes, void *stream) {
-  if (int rc = check_gnn_common("lbm_step_gnn", 1, nx, ny, params, n_rounds)) return rc;
-  if (!g_src || !g_dst) return fail(LBM_EINVAL, "lbm_step_gnn: null pointer");
-  if (!(tau > 0.0f)) return fail(LBM_EINVAL, "lbm_step_gnn: tau must be positive");
-  size_t bytes = (size_t)9 * nx * ny * sizeof(float);
-  if (lbm::overlap(g_src, g_dst, bytes))
-    return fail(LBM_EINVAL, "lbm_step_gnn: source and destination overlap");
-  if (fb && (!fb->flags || !fb->mass))
-    return fail(LBM_EINVAL, "lbm_step_gnn: fallback needs flags and mass pointers");
-  size_t need = step_workspace_bytes(nx, ny, n_rounds);
-  if (!workspace || ws_bytes < need)
-    return fail(LBM_EWORKSPACE, "lbm_step_gnn: workspace needs %zu bytes", need);
-  if (int rc = check_device()) return rc;
-  hipStream_t s = (hipStream_t)stream;
+// lbm_step_gnn on a given scratch of forward_scratch(nx * ny) bytes or more.
+static int step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                    const float *params, int n_rounds, const lbm_fallback *fb, void *workspace,
+                    hipStream_t s) {
   if (int rc = launch_forward(true, g_src, g_dst, 1, nx, ny, nullptr, tau, params, n_rounds,
                               nullptr, nullptr, workspace, fb, s))
     return rc;
@@ -1009,4 +998,81 @@ extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, fl
   const ForwardScratch W = forward_scratch((long long)nx * ny);
   return launch_gate(g_src, g_dst, nx, ny, tau, 0, 0.0f, fb, at(workspace, W.pmass2),
                      at(workspace, W.ctrl), s);
+}
+
+static int check_step_gnn(const char *who, const float *g_src, float *g_dst, int nx, int ny,
+                          float tau, const float *params, int n_rounds, const lbm_fallback *fb) {
+  if (int rc = check_gnn_common(who, 1, nx, ny, params, n_rounds)) return rc;
+  if (!g_src || !g_dst) return fail(LBM_EINVAL, "%s: null pointer", who);
+  if (!(tau > 0.0f)) return fail(LBM_EINVAL, "%s: tau must be positive", who);
+  size_t bytes = (size_t)9 * nx * ny * sizeof(float);
+  if (lbm::overlap(g_src, g_dst, bytes))
+    return fail(LBM_EINVAL, "%s: source and destination overlap", who);
+  if (fb && (!fb->flags || !fb->mass))
+    return fail(LBM_EINVAL, "%s: fallback needs flags and mass pointers", who);
+  return LBM_OK;
+}
+
+extern "C" int lbm_step_gnn(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                            const float *params, int n_rounds, const lbm_fallback *fb,
+                            void *workspace, size_t ws_bytes, void *stream) {
+  if (int rc = check_step_gnn("lbm_step_gnn", g_src, g_dst, nx, ny, tau, params, n_rounds, fb))
+    return rc;
+  size_t need = step_workspace_bytes(nx, ny, n_rounds);
+  if (!workspace || ws_bytes < need)
+    return fail(LBM_EWORKSPACE, "lbm_step_gnn: workspace needs %zu bytes", need);
+  if (int rc = check_device()) return rc;
+  return step_gnn(g_src, g_dst, nx, ny, tau, params, n_rounds, fb, workspace,
+                  (hipStream_t)stream);
+}
+
+// ------------------------------------------------- allocation-free step ---
+
+// Scratch of lbm_step_gnn_noalloc: the forward scratch of the largest lattice
+// it accepts, as a file-scope device array.  Every device the library runs
+// on holds its own copy, at its own address.  In host code `scratch` names a
+// host-side stand-in, not device memory: the device address of the current
+// device's copy is looked up once with hipGetSymbolAddress and kept, and only
+// that address is ever handed to kernels.
+constexpr size_t kNoAllocBytes = forward_scratch(LBM_NOALLOC_MAX_NODES).total;
+static_assert(kNoAllocBytes < (17u << 20), "the static scratch is documented as ~16.6 MiB");
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[64];  // device address of `scratch`, per device index
+
+static int noalloc_scratch(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess)
+    return fail(LBM_EDEVICE, "lbm_step_gnn_noalloc: hipGetDevice failed");
+  if (dev < 0 || dev >= 64)
+    return fail(LBM_EUNSUPPORTED, "lbm_step_gnn_noalloc: device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LBM_EDEVICE, "lbm_step_gnn_noalloc: hipGetSymbolAddress: %s",
+                  hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return LBM_OK;
+}
+
+extern "C" int lbm_step_gnn_noalloc(const float *g_src, float *g_dst, int nx, int ny, float tau,
+                                    const float *params, int n_rounds, const lbm_fallback *fb,
+                                    void *stream) {
+  const char *who = "lbm_step_gnn_noalloc";
+  if (int rc = check_step_gnn(who, g_src, g_dst, nx, ny, tau, params, n_rounds, fb)) return rc;
+  if ((long long)nx * ny > LBM_NOALLOC_MAX_NODES)
+    return fail(LBM_EINVAL, "%s: %d x %d lattice has more than the %d nodes its static scratch holds",
+                who, nx, ny, LBM_NOALLOC_MAX_NODES);
+  if (int rc = check_device()) return rc;
+  void *ws = nullptr;
+  if (int rc = noalloc_scratch(&ws)) return rc;
+  // Everything the step reads from its scratch is written earlier in the same
+  // step (the weight packing also zeroes the gate's arrival counts), so what
+  // an earlier call left there does not matter.
+  return step_gnn(g_src, g_dst, nx, ny, tau, params, n_rounds, fb, ws, (hipStream_t)stream);
 }

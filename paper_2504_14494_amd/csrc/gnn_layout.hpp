@@ -43,7 +43,7 @@ inline BlobLayout blob_layout(int R) {
   return L;
 }
 
-inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Activations kept by gnn_forward for gnn_backward, per node:
 //   x   [16]  BF16 normalised features (12 used, 4 zero)
@@ -88,7 +88,7 @@ struct ForwardScratch {
   size_t pack, hA, hB, pmass, pflag, pmass2, ctrl, total;
 };
 
-inline ForwardScratch forward_scratch(long long nodes) {
+constexpr ForwardScratch forward_scratch(long long nodes) {
   ForwardScratch F{};
   size_t n = (size_t)nodes, o = 0;
   F.pack = o; o += kPackBytes;

@@ -16,6 +16,7 @@ from ._lib import LbmFallback, check
 from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
+           "lbm_step_gnn_noalloc",
            "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
            "GnnMse", "simple_forward", "lbm_step_simple", "lbm_step_simple_channel",
            "gnn_gelu_rate", "collide"]
@@ -113,6 +114,24 @@ def lbm_step_gnn(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.T
     rc = L.lbm_step_gnn(_ptr(src), _ptr(dst), nx, ny, float(tau), _ptr(blob), rounds, fb,
                         _ptr(buf), buf.numel(), _stream())
     check(rc, "lbm_step_gnn")
+    return dst
+
+
+def lbm_step_gnn_noalloc(src: torch.Tensor, dst: torch.Tensor, tau: float, blob: torch.Tensor,
+                         rounds: int = 2, fallback: Fallback = None):
+    """lbm_step_gnn on the library's static scratch: no workspace, nothing
+    allocated (lattices of at most LBM_NOALLOC_MAX_NODES nodes; calls on one
+    GPU must not overlap)."""
+    _need(src, torch.float32, "src")
+    _need(dst, torch.float32, "dst")
+    if src.dim() != 3 or src.shape[1] != 9 or src.shape != dst.shape:
+        raise ValueError("src and dst must both be [ny, 9, nx]")
+    _check_blob(blob, rounds)
+    ny, nx = int(src.shape[0]), int(src.shape[2])
+    fb = ctypes.byref(fallback.struct()) if fallback is not None else None
+    rc = _lib.load().lbm_step_gnn_noalloc(_ptr(src), _ptr(dst), nx, ny, float(tau), _ptr(blob),
+                                          rounds, fb, _stream())
+    check(rc, "lbm_step_gnn_noalloc")
     return dst
 
 

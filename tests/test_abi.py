@@ -91,9 +91,26 @@ def test_every_entry_point_rejects_bad_arguments_before_device_work():
         ("lbm_step_simple_channel", (a, b, 4, 4, 0.7, 1e-4, c, None, d, 16, None), EWORKSPACE),
         ("simple_forward", (a, a, 1, 4, 4, b, c, None, None, 0, d, 1 << 30, None), EINVAL),
         ("simple_forward", (a, b, 1, 4, 4, b, c, None, e, 16, d, 1 << 30, None), EWORKSPACE),
+        ("lbm_step_gnn_noalloc", (a, b, 4, 4, -1.0, c, 2, None, None), EINVAL),
+        ("lbm_step_gnn_noalloc", (a, b, 4, 4, 0.7, c, 0, None, None), EINVAL),
+        ("lbm_step_gnn_noalloc", (a, a, 4, 4, 0.7, c, 2, None, None), EINVAL),
     ]
     for name, args, code in cases:
         rc = getattr(L, name)(*args)
         assert rc == code, (name, rc, L.lbm_last_error())
         # the thread-local message names the entry point that failed
         assert L.lbm_last_error().decode().startswith(name.split("_f64")[0]), name
+
+
+def test_noalloc_step_rejects_lattices_beyond_its_static_scratch():
+    """lbm_step_gnn_noalloc holds at most LBM_NOALLOC_MAX_NODES nodes; larger
+    lattices are refused before any device work (the addresses below are
+    never dereferenced)."""
+    L = _lib.load()
+    a, b, c = 1 << 40, 2 << 40, 3 << 40
+    assert L.lbm_step_gnn_noalloc(a, b, 256, 256 + 1, 0.7, c, 2, None, None) == EINVAL
+    assert b"static scratch" in L.lbm_last_error()
+    assert L.lbm_step_gnn_noalloc(a, b, _lib.LBM_NOALLOC_MAX_NODES + 1, 1, 0.7, c, 2, None,
+                                  None) == EINVAL
+    text = open(os.path.join(ROOT, "include", "lbmgnn.h")).read()
+    assert f"#define LBM_NOALLOC_MAX_NODES {_lib.LBM_NOALLOC_MAX_NODES}" in text
