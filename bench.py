@@ -15,8 +15,12 @@ rocprofv3 counters).  Beside it:
                needs (measured and projected from the large-lattice MLUPS);
                and the paper's resolution study (observed order, Eq. 6) and
                Reynolds-number sweep, trained network beside plain BGK, and
-               its Poiseuille channel (Eq. 5) with plain BGK;
-  cpu_baseline the FP64 CPU oracle timed on the host on a bounded sample.
+               its Poiseuille channel (Eq. 5) with plain BGK; the long
+               high-Re rollout (2048^2, Re = 1e4, 20000 steps) of both trained
+               networks and of BGK against the FP64 oracle's stored energies;
+  cpu_baseline the FP64 CPU oracle timed on the host on a bounded sample
+               (plain BGK; the corrected collisions' host rates sit in the
+               gnn and gnn_per_node legs).
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -241,6 +245,9 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     # which head moves the rollout error (relaxation time or correction)
     out["head_ablation"] = {"message_passing": experiments.head_ablation(tr.blob, rounds=2),
                             "fig2_network": experiments.head_ablation(tr0.blob, rounds=0)}
+    # the long high-Re rollout with both trained networks and plain BGK,
+    # against the FP64 oracle's stored energies of the same flow
+    out["long_rollout_2048_re1e4"] = long_rollout_leg({2: tr.blob, 0: tr0.blob})
     # the trained per-node network on the forced channel (Poiseuille), the
     # same Reynolds numbers as the BGK channel study
     pois = experiments.poiseuille_study(blob=tr0.blob)
@@ -253,6 +260,42 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
                                            "fallback_steps": r["fallback_steps"],
                                            "seconds": round(r["seconds"], 2)}
                                           for r in pois["rows"]]}
+    return out
+
+
+LONG_REFERENCE = os.path.join(ROOT, "tests", "golden", "tgv2048_re1e4_energy.txt")
+
+
+def long_rollout_leg(blobs):
+    """Taylor-Green 2048^2, Re = 1e4, u0 = 0.05, 20000 steps with per-step
+    fallback gate: the trained message-passing network, the trained Fig. 2
+    network and plain BGK, each against the FP64 oracle's energies of the
+    256^2 injection (stored data written by the oracle, read as text)."""
+    import numpy as np
+    from paper_2504_14494_amd import experiments
+    ref = np.loadtxt(LONG_REFERENCE) if os.path.exists(LONG_REFERENCE) else None
+    out = {"workload": "TGV 2048x2048, Re=1e4, u0=0.05, uniform density, 20000 steps, "
+                       "energy of the 256x256 injection every 2000 steps",
+           "reference": "FP64 oracle plain BGK (tests/golden/tgv2048_re1e4_energy.txt)"
+           if ref is not None else None}
+    for name, blob, rounds in (("message_passing", blobs[2], 2), ("fig2_network", blobs[0], 0),
+                               ("bgk", None, 2)):
+        rep = experiments.long_rollout(blob, rounds=rounds, reference=ref)
+        row = {"mlups": round(rep["mlups"], 1), "ms_per_step": round(rep["ms_per_step"], 4),
+               "max_mass_drift_fp64": float(f"{rep['max_mass_drift']:.3g}"),
+               "energy_err_vs_analytic_at_end":
+                   float(f"{rep['samples'][-1]['energy_err_vs_analytic']:.4g}")}
+        if blob is not None:
+            row["fallback_steps"] = rep["fallback_steps"]
+        if ref is not None:
+            row["energy_err_vs_oracle"] = [float(f"{r['energy_err_vs_oracle']:.3g}")
+                                           for r in rep["samples"][1:]]
+            row["max_energy_err_vs_oracle"] = float(f"{rep['max_energy_err_vs_oracle']:.4g}")
+            row["decay_err_vs_oracle_at_end"] = float(
+                f"{rep['samples'][-1]['decay_err_vs_oracle']:.4g}")
+        out[name] = row
+    if ref is not None:
+        out["oracle_energy"] = [float(f"{e:.10g}") for e in ref[:, 1]]
     return out
 
 
@@ -283,6 +326,7 @@ def studies_leg(blob):
                   "bgk_first_bad_step": r["bgk"]["first_bad_step"],
                   "gnn_first_bad_step": r["gnn"]["first_bad_step"],
                   "gnn_fallback_steps": r["gnn"]["fallback_steps"],
+                  "gnn_omega_above_2_nodes_max": r["gnn"]["omega_above_2_nodes_max"],
                   "bgk_energy_err": float(f"{r['bgk']['energy_err']:.4g}"),
                   "gnn_energy_err": float(f"{r['gnn']['energy_err']:.4g}")} for r in sw["runs"]]
     # FP32 (the product path) and FP64: near tau = 1/2 the slowest channel
@@ -382,6 +426,62 @@ def cpu_leg():
                             "sample": f"{n}x{n}, {steps} steps, {dt:.1f} s"}}
 
 
+def _oracle_gnn_sample(args):
+    """One oracle corrected-collision evaluation (a child process); returns
+    its seconds.  kind "lattice": the whole n^2 lattice; "nodes": `count`
+    random nodes of an n^2 lattice, each from its own neighbourhood."""
+    kind, n, rounds, count, seed = args
+    import numpy as np
+    import oracle
+    from paper_2504_14494_amd import inputs
+    rho, ux, uy = inputs.tgv_velocity(n, n, 0.04, x0=3.0 * seed)
+    f = oracle.init_equilibrium(rho, ux, uy)
+    blob = inputs.gnn_blob(0, rounds, s_delta=1e-4).astype(np.float64)
+    tau = inputs.tgv_params(n, 0.04, 1000.0)[1]
+    act = 1 if rounds == 0 else 0
+    t0 = time.perf_counter()
+    if kind == "lattice":
+        oracle.gnn_collide(f, tau, blob, rounds, mode=0, act=act)
+    else:
+        nodes = np.random.default_rng(seed).integers(0, n * n, count)
+        oracle.gnn_collide_nodes(f, tau, blob, nodes, rounds, mode=0)
+    return time.perf_counter() - t0
+
+
+def gnn_cpu_leg():
+    """The FP64 oracle's corrected collision (message passing, 2 rounds; and
+    the Fig. 2 per-node network) on the host, in million node updates per
+    second: one process on one core, then one process per core (at most 16)
+    each on its own lattice; and the message-passing collision on 4096
+    sampled nodes of the 2048^2 workload (each from its 5 x 5
+    neighbourhood)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import oracle
+    oracle.build(force=False)
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    out = {}
+    for name, rounds, n in (("message_passing", 2, 256), ("fig2_network", 0, 1024)):
+        dt = _oracle_gnn_sample(("lattice", n, rounds, 0, 0))
+        with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
+            secs = list(ex.map(_oracle_gnn_sample,
+                               [("lattice", n, rounds, 0, k) for k in range(procs)]))
+        out[name] = {
+            "value": procs * n * n / max(secs) / 1e6, "unit": "MLUPS", "cores": procs,
+            "kind": "oracle",
+            "sample": f"FP64 oracle corrected collision (no streaming), {procs} processes x "
+                      f"{n}x{n} TGV lattice, one core each (slowest {max(secs):.1f} s)",
+            "single_core": {"value": n * n / dt / 1e6, "unit": "MLUPS", "cores": 1,
+                            "sample": f"{n}x{n}, {dt:.1f} s"}}
+    dt = _oracle_gnn_sample(("nodes", 2048, 2, 4096, 1))
+    out["message_passing"]["sampled_2048"] = {
+        "value": 4096 / dt / 1e6, "unit": "MLUPS", "cores": 1,
+        "sample": f"4096 random nodes of the 2048x2048 workload, each from its 5x5 "
+                  f"neighbourhood, one core, {dt:.1f} s"}
+    return out
+
+
 def _committed(path, src_hash):
     """A committed rocprofv3 counter summary, or None if it is missing or was
     taken on a different kernel source."""
@@ -408,7 +508,7 @@ def main():
     ap.add_argument("--re", type=float, default=1000.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gnn", action="store_true")
-    ap.add_argument("--gnn-steps", type=int, default=20)
+    ap.add_argument("--gnn-steps", type=int, default=50)
     ap.add_argument("--no-fixed-error", action="store_true",
                     help="skip training the network (about 10 s) and the rollout comparison")
     args = ap.parse_args()
@@ -477,7 +577,7 @@ def main():
             out["gnn"] = {"error": repr(e)}
     if not args.no_gnn:
         try:
-            out["gnn_per_node"] = simple_leg(args.n, max(10, args.steps // 10), 5,
+            out["gnn_per_node"] = simple_leg(args.n, max(100, args.steps // 10), 5,
                                              bgk["ms_per_step"])
         except Exception as e:
             out["gnn_per_node"] = {"error": repr(e)}
@@ -488,6 +588,15 @@ def main():
             out["fixed_error"] = {"error": repr(e)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_leg()
+        if not args.no_gnn:
+            try:
+                g_cpu = gnn_cpu_leg()
+                if "gnn" in out:
+                    out["gnn"]["cpu_baseline"] = g_cpu["message_passing"]
+                if "gnn_per_node" in out:
+                    out["gnn_per_node"]["cpu_baseline"] = g_cpu["fig2_network"]
+            except Exception as e:
+                out["gnn_cpu_baseline_error"] = repr(e)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -148,55 +148,87 @@ def head_ablation(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_fine=
 
 
 
-def _energy(ux, uy):
-    return 0.5 * float(((ux.double() ** 2) + (uy.double() ** 2)).sum().item())
-
-
 def long_rollout(blob, rounds=2, n=2048, u0=0.05, re=1e4, steps=20000, sample_every=2000,
-                 n_sample=256, threshold=1e-6):
-    """Long corrected rollout with the per-step fallback gate, beside an FP64
-    BGK run of the same flow.  Every `sample_every` steps both are sampled on
-    every (n/n_sample)-th node (injection) and the kinetic energies are
-    compared; mass and momentum are summed in FP64 on the GPU."""
-    tau = _tau(u0, re, n)
+                 n_sample=256, threshold=1e-6, reference=None, nodes=()):
+    """Long Taylor-Green rollout at high Reynolds number (uniform density, f
+    at equilibrium at t = 0) with the corrected collision and the per-step
+    fallback gate, or with plain BGK when blob is None.  Every
+    `sample_every` steps the velocity field is restricted by injection to
+    n_sample^2 (every (n / n_sample)-th node) and its kinetic energy
+    1/2 sum |u|^2 is compared with
+      - `reference`: rows (step, energy, mass, ...) of the FP64 oracle's
+        plain-BGK run of the same flow on the same restriction, when given
+        (the error of the energy and of its decay E(t) / E(0));
+      - the analytic decay E(0) exp(-4 nu k^2 t), nu = (tau - 1/2) / 3.
+    Mass and momentum are summed in FP64 by lbm_moments (drift relative to
+    the initial state).  `nodes`: (y, x) lattice nodes whose velocity is
+    reported at every sample."""
+    tau32 = float(np.float32(_tau(u0, re, n)))
     rho, ux, uy = inputs.tgv_velocity(n, n, u0, dtype=np.float32)
-    lat = gnn.GnnLattice(n, n, blob, rounds, threshold).init(rho, ux, uy)
-    ref = lbm.Lattice(n, n, dtype=torch.float64).init(*inputs.tgv_velocity(n, n, u0))
+    if blob is None:
+        lat = lbm.Lattice(n, n).init(rho, ux, uy)
+    else:
+        lat = gnn.GnnLattice(n, n, blob, rounds, threshold).init(rho, ux, uy)
     c = n // n_sample
-    _, _, _, s0 = lat.moments()
-    s0 = s0.cpu().numpy()
-    nu = (float(np.float32(tau)) - 0.5) / 3.0
-    k2 = 2.0 * (2.0 * math.pi / n) ** 2
-    rows, done, ms = [], 0, 0.0
+    ref = None if reference is None else {int(r[0]): r for r in np.asarray(reference)}
+    nu = (tau32 - 0.5) / 3.0
+    k2 = (2.0 * math.pi / n) ** 2
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t32 = float(np.float32(tau))
+    ny_, nx_ = (torch.as_tensor([p[0] for p in nodes], dtype=torch.long),
+                torch.as_tensor([p[1] for p in nodes], dtype=torch.long))
+
+    def sample(step):
+        _, gx, gy, sums = lat.moments(fields=True)
+        s = sums.cpu().numpy()
+        sx, sy = gx[::c, ::c].double(), gy[::c, ::c].double()
+        row = {"step": step, "energy": 0.5 * float((sx * sx + sy * sy).sum().item()),
+               "mass": float(s[0]), "momentum": [float(s[1]), float(s[2])],
+               "min_f": float(s[6]), "n_negative": int(s[7])}
+        if nodes:
+            row["node_velocity"] = torch.stack([gx.cpu()[ny_, nx_], gy.cpu()[ny_, nx_]],
+                                               1).double().tolist()
+        if blob is not None:
+            row["fallback_steps"] = int(lat.n_fallback.item())
+        return row
+
+    rows = [sample(0)]
+    done, ms = 0, 0.0
     while done < steps:
         k = min(sample_every, steps - done)
         e0.record()
-        lat.step_gnn(t32, k)
+        if blob is None:
+            lat.step_bgk(tau32, k)
+        else:
+            lat.step_gnn(tau32, k)
         e1.record()
-        ref.step_bgk(tau, k)
         torch.cuda.synchronize()
         ms += e0.elapsed_time(e1)
         done += k
-        _, gx, gy, sums = lat.moments(fields=True)
-        gref = lbm.lbm_restrict(ref.a, 1, tau, tau, pull=False, unstream=False)
-        rx, ry = _velocity(gref)
-        e_gnn = _energy(gx[::c, ::c], gy[::c, ::c])
-        e_ref = _energy(rx[::c, ::c], ry[::c, ::c])
-        e_an = _energy(*[torch.as_tensor(a[::c, ::c]) for a in inputs.tgv_velocity(n, n, u0)[1:]]) \
-            * math.exp(-2.0 * nu * k2 * done)
-        s = sums.cpu().numpy()
-        rows.append({"step": done, "energy_err_vs_fp64": abs(e_gnn - e_ref) / e_ref,
-                     "energy_err_fp64_vs_analytic": abs(e_ref - e_an) / e_an,
-                     "mass_drift": abs(s[0] - s0[0]) / s0[0],
-                     "momentum": [float(s[1]), float(s[2])],
-                     "fallback_steps": int(lat.n_fallback.item()),
-                     "min_f": float(s[6])})
-    return {"n": n, "u0": u0, "re": re, "tau": tau, "steps": steps,
-            "mlups": n * n * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
-            "samples": rows}
+        rows.append(sample(done))
+    E0, M0 = rows[0]["energy"], rows[0]["mass"]
+    for r in rows:
+        t = r["step"]
+        ea = E0 * math.exp(-4.0 * nu * k2 * t)
+        r["energy_err_vs_analytic"] = abs(r["energy"] - ea) / ea
+        r["mass_drift"] = abs(r["mass"] - M0) / M0
+        if ref is not None and t in ref:
+            er, er0 = float(ref[t][1]), float(ref[0][1])
+            r["energy_err_vs_oracle"] = abs(r["energy"] - er) / er
+            r["decay_err_vs_oracle"] = abs(r["energy"] / E0 - er / er0) / (er / er0)
+    out = {"n": n, "u0": u0, "re": re, "tau": tau32, "steps": steps, "n_sample": n_sample,
+           "collision": "bgk" if blob is None else ("fig2-network" if rounds == 0
+                                                    else "message-passing"),
+           "mlups": n * n * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
+           "samples": rows,
+           "max_mass_drift": max(r["mass_drift"] for r in rows)}
+    if ref is not None:
+        errs = [r["energy_err_vs_oracle"] for r in rows if "energy_err_vs_oracle" in r]
+        out["max_energy_err_vs_oracle"] = max(errs) if errs else None
+        out["energy_err_vs_oracle_at_end"] = rows[-1].get("energy_err_vs_oracle")
+    if blob is not None:
+        out["fallback_steps"] = rows[-1]["fallback_steps"]
+    return out
 
 
 def _analytic(n, u0, tau32, t):
@@ -315,6 +347,18 @@ def tgv_validation(blob=None, rounds=2, n=64, re=100.0, u0=0.04, checkpoints=(10
     return {"n": n, "re": re, "u0": u0, "tau": tau32, "start": start, "rows": rows}
 
 
+def fast_relaxation_nodes(g32: torch.Tensor, tau32: float, blob, rounds: int) -> int:
+    """Number of nodes of a (post-collision) state whose next corrected
+    collision relaxes faster than omega = 2, i.e. tau * tau_adj < 1/2 with
+    tau_adj = 1/2 + sigmoid(z_0) from the network's head (no clamp is
+    applied to tau_adj; the fallback gate catches what such nodes do)."""
+    pre = lbm.lbm_stream(g32)[None]
+    tau_t = torch.full((1,), tau32, dtype=torch.float32, device=g32.device)
+    _, z = gnn.collide(pre, tau_t, blob, rounds, want_z=True)
+    tau_adj = 0.5 + torch.sigmoid(z[..., 0].double())
+    return int((tau32 * tau_adj < 0.5).sum().item())
+
+
 def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
                     re_list=(100, 200, 400, 800, 1600, 3200), steps=20000, every=1000):
     """Taylor-Green runs on an n^2 lattice over a range of Reynolds numbers.
@@ -322,8 +366,10 @@ def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
     non-finite or negative population ends the run ("first_bad_step").  The
     corrected collision runs with the per-step fallback gate, so its first
     step that fell back to BGK and the number of such steps are reported as
-    well.  Energy and velocity errors are against the analytic decay at the
-    last step reached."""
+    well, and at every check the number of nodes whose effective relaxation
+    rate exceeds 2 (the most found at any check, and at the last).  Energy
+    and velocity errors are against the analytic decay at the last step
+    reached."""
     out = []
     for re in re_list:
         tau32 = float(np.float32(_tau(u0, re, n)))
@@ -334,11 +380,14 @@ def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
             lat = _lattice(n, u0, tau32, b, rounds)
             e0 = tgv_state_errors(lat.a, n, u0, tau32, 0)["energy"]
             done, first_bad, first_fb, st = 0, None, None, None
+            fast = []
             while done < steps:
                 k = min(every, steps - done)
                 _advance(lat, b, tau32, k)
                 done += k
                 st = tgv_state_errors(lat.a, n, u0, tau32, done)
+                if b is not None and st["finite"]:
+                    fast.append(fast_relaxation_nodes(lat.a, tau32, b, rounds))
                 if b is not None and first_fb is None and int(lat.n_fallback.item()) > 0:
                     first_fb = done
                 if not st["finite"] or st["n_negative"] > 0:
@@ -352,6 +401,8 @@ def stability_sweep(blob=None, rounds=2, n=64, u0=0.04,
             if b is not None:
                 r["fallback_steps"] = int(lat.n_fallback.item())
                 r["first_fallback_by_step"] = first_fb
+                r["omega_above_2_nodes_max"] = max(fast) if fast else None
+                r["omega_above_2_nodes_last"] = fast[-1] if fast else None
             row[name] = r
         out.append(row)
     return {"n": n, "u0": u0, "steps": steps, "check_every": every, "runs": out}
@@ -445,6 +496,9 @@ def main(argv=None):
     ap.add_argument("--scaling", default="diffusive", choices=["diffusive", "acoustic"])
     ap.add_argument("--fp64", action="store_true", help="BGK runs in FP64 (resolution, poiseuille)")
     ap.add_argument("--steps", type=int, default=20000, help="long-rollout steps")
+    ap.add_argument("--reference", default="",
+                    help="long rollout: file of the FP64 oracle's energies (step, energy, ...) "
+                         "on the same restriction")
     args = ap.parse_args(argv)
     t0 = time.perf_counter()
     blob = None
@@ -474,7 +528,8 @@ def main(argv=None):
         out = {f"{name}_{start}_start": tgv_validation(b, rounds=args.rounds, start=start)
                for start in ("equilibrium", "slow") for name, b in (("bgk", None), ("gnn", blob))}
     else:
-        out = long_rollout(blob, rounds=args.rounds, steps=args.steps)
+        ref = np.loadtxt(args.reference) if args.reference else None
+        out = long_rollout(blob, rounds=args.rounds, steps=args.steps, reference=ref)
     out["wall_seconds"] = round(time.perf_counter() - t0, 1)
     print(json.dumps(out))
 

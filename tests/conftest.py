@@ -18,3 +18,17 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def trained():
+    """Both networks trained by the library on its own data, in the full
+    configuration the benchmark uses (same seeds, so the same networks):
+    {2: message-passing blob, 0: Fig. 2 per-node blob}.  About 10 s of GPU."""
+    from paper_2504_14494_amd import train
+    data = train.datasets(train.DataConfig())
+    out = {}
+    for rounds in (2, 0):
+        tr, _ = train.train(train.DataConfig(), steps=2000, batch=32, rounds=rounds, data=data)
+        out[rounds] = tr.blob
+    return out

@@ -71,3 +71,57 @@ def test_golden_tgv_fp32_library():
               f"energy error GPU {got['energy_err']:.6e} oracle {ee:.6e}")
         assert abs(got["vel_err"] - ve) <= tol
         assert abs(got["energy_err"] - ee) <= 2 * tol
+
+
+# ------------------------------------------- long high-Re rollout reference ---
+# tests/golden/tgv2048_re1e4_energy.txt, written by make_cfg5.py from the FP64
+# oracle: 2048^2 Taylor-Green, Re = 1e4, u0 = 0.05, uniform density, 20000
+# steps; energy of the 256^2 injection, total mass and eight node velocities
+# every 2000 steps.
+
+LONG = os.path.join(os.path.dirname(GOLDEN), "tgv2048_re1e4_energy.txt")
+LONG_NODES = [(0, 0), (0, 2040), (2040, 8), (1024, 1024), (512, 1536), (1536, 512), (8, 1000),
+              (2000, 2000)]
+
+
+def test_long_rollout_reference_layout_and_invariants():
+    """The stored file has the generator's layout; its total mass is
+    conserved (FP64 roundoff only); its energy follows the analytic decay
+    E0 exp(-4 nu k^2 t), nu = (tau - 1/2)/3, within the transient that the
+    uniform-density start launches (the missing Taylor-Green pressure puts
+    O(u0^2) waves and harmonics into the velocity field: measured at most
+    3.7e-3 of the energy, bar 5e-3).  A wrong viscosity by a factor 2 or a
+    wrong wavenumber would leave that band by the end of the run."""
+    import numpy as np
+    ref = np.loadtxt(LONG)
+    assert ref.shape == (11, 3 + 2 * len(LONG_NODES))
+    assert list(ref[:, 0]) == list(range(0, 20001, 2000))
+    head = open(LONG).read()
+    assert " ".join(f"{y},{x}" for y, x in LONG_NODES) in head
+    tau = float(np.float32(3.0 * 0.05 * 2048 / 1e4 + 0.5))
+    assert f"tau = {tau!r}" in head
+    nu, k2 = (tau - 0.5) / 3.0, (2.0 * math.pi / 2048) ** 2
+    for row in ref:
+        decay = math.exp(-4.0 * nu * k2 * row[0])
+        assert abs(row[1] / ref[0, 1] / decay - 1.0) <= 5e-3, row[0]
+        assert abs(row[2] - 2048 * 2048) <= 1e-11 * 2048 * 2048
+    # the velocity field at the sampled nodes stays within the amplitude
+    assert np.abs(ref[:, 3:]).max() <= 0.05
+
+
+def test_long_rollout_reference_initial_row_is_the_oracles(orc):
+    """Row 0 re-derived with the oracle: the equilibrium start of the same
+    FP32-rounded Taylor-Green field, its injection energy, mass and sampled
+    node velocities."""
+    import numpy as np
+    from paper_2504_14494_amd import inputs
+    ref = np.loadtxt(LONG)
+    n = 2048
+    _, ux, uy = inputs.tgv_velocity(n, n, 0.05, dtype=np.float32)
+    ux, uy = ux.astype(np.float64)[::8, ::8], uy.astype(np.float64)[::8, ::8]
+    f = orc.init_equilibrium(np.ones_like(ux), ux, uy)
+    _, vx, vy = orc.moments(f)
+    assert abs(0.5 * float((vx * vx + vy * vy).sum()) - ref[0, 1]) <= 1e-12 * ref[0, 1]
+    for k, (y, x) in enumerate(LONG_NODES):
+        assert abs(vx[y // 8, x // 8] - ref[0, 3 + 2 * k]) <= 1e-15
+        assert abs(vy[y // 8, x // 8] - ref[0, 4 + 2 * k]) <= 1e-15

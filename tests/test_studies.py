@@ -158,3 +158,80 @@ def test_poiseuille_refinement_is_second_order_for_bgk():
     for r in rep["rows"]:
         assert abs(r["max_rel_err"] - abs(r["slip_rel_closed_form"])) < 2e-3 * abs(r["slip_rel_closed_form"]) + 1e-7
     assert 1.8 < rep["alpha"][0] < 2.3
+
+
+def _tame_head(seed):
+    """A seeded network whose relaxation-time head is scaled down (row 0 of
+    W_h by 0.02, b_h[0] = 0), so that tau_adj stays within about 1 % of 1: at
+    tau near 1/2 that puts the effective omega = 1/(tau tau_adj) on both sides
+    of 2 without sending every step to the fallback."""
+    blob = inputs.gnn_blob(seed, 2, s_delta=1e-4)
+    o, (_, cols) = inputs.blob_offsets(2)["Wh"]
+    blob[o:o + cols] *= np.float32(0.02)
+    blob[inputs.blob_offsets(2)["bh"][0]] = 0.0
+    return torch.as_tensor(blob, device="cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("re", [1600.0, 3200.0])
+@pytest.mark.parametrize("net", ["trained", "seeded"])
+def test_sweep_trajectory_steps_match_the_oracle_near_tau_one_half(orc, trained, re, net):
+    """The Reynolds sweep's regime (64^2, u0 = 0.04; tau = 0.5048 at Re = 1600
+    and 0.5024 at Re = 3200), gate on, along the trajectory: at steps 0, 100
+    and 1000 of the library's gated run, its next step is compared with the
+    oracle's streaming plus gated corrected collision from the same state.
+
+    - The fallback decision agrees (BF16-emulating oracle, the kernel's
+      storage precision).
+    - f* within the benchmark spec's 1e-3 of the FP64 oracle.
+    - The correction delta* = f* - f*_BGK: at every node within 5e-2 of its
+      largest value against the BF16-emulating oracle, and as a field within
+      5e-2 of the FP64 oracle.  Near tau = 1/2 the correction is mostly
+      (1/tau_adj - 1)(f - f^eq)/tau, and where the trained z0 is near zero
+      the ~1 % BF16-storage error of the head output is a large share of it,
+      so node by node the FP64 comparison measures BF16 storage, not the
+      kernel (its value is printed)."""
+    n, u0 = 64, 0.04
+    tau32 = float(np.float32(experiments._tau(u0, re, n)))
+    blob = trained[2] if net == "trained" else _tame_head(31)
+    blob64 = blob.double().cpu().numpy()
+    lat = experiments._lattice(n, u0, tau32, blob, 2)
+    w = orc.lattice()[2][:, None, None]
+    done = 0
+    for t in (0, 100, 1000):
+        lat.step_gnn(tau32, t - done, graph=True)
+        src = lat.a.clone()
+        mass_prev = float(lat.fallback.mass.item())
+        before = int(lat.n_fallback.item())
+        lat.step_gnn(tau32, 1)
+        done = t + 1
+        torch.cuda.synchronize()
+        got = inputs.rows_to_planes(lat.a.double().cpu().numpy()) + w
+        fpre = orc.stream(inputs.rows_to_planes(src.double().cpu().numpy()) + w)
+        ref1, flags, _ = orc.gnn_collide_gated(fpre, tau32, blob64, 1e-6, mass_prev, 2, mode=1)
+        ref0, z = orc.gnn_collide(fpre, tau32, blob64, 2, mode=0, want_z=True)
+        fell = int(lat.n_fallback.item()) - before
+        bgk = orc.collide_bgk(fpre, tau32)
+        # nodes whose effective relaxation rate exceeds 2 (tau tau_adj < 1/2)
+        fast = int((tau32 * (0.5 + 1.0 / (1.0 + np.exp(-z[..., 0]))) < 0.5).sum())
+        msg = f"{net} Re={re:g} step {t}: oracle flags {flags}, GPU fell back {fell}, " \
+              f"omega_eff > 2 at {fast} nodes"
+        assert fell == (1 if flags else 0), msg
+        if flags:
+            rel = _rel(got, bgk)
+            msg += f", fallback f* vs oracle BGK rel-L2 {rel:.2e}"
+            assert rel <= 1e-6, msg
+        else:
+            rel = _rel(got, ref0)
+            d, d1, d0 = got - bgk, ref1 - bgk, ref0 - bgk
+            node1 = float(np.abs(d - d1).max() / np.abs(d1).max())
+            node0 = float(np.abs(d - d0).max() / np.abs(d0).max())
+            msg += (f", f* rel-L2 {rel:.2e}; correction vs BF16 oracle per node {node1:.2e}, "
+                    f"vs FP64 rel-L2 {_rel(d, d0):.2e} (per node {node0:.2e})")
+            assert rel <= 1e-3, msg
+            assert node1 <= 5e-2, msg
+            assert _rel(d, d0) <= 5e-2, msg
+        print(msg)
