@@ -245,6 +245,18 @@ def fixed_error_leg(mlups_bgk, mlups_gnn):
     # which head moves the rollout error (relaxation time or correction)
     out["head_ablation"] = {"message_passing": experiments.head_ablation(tr.blob, rounds=2),
                             "fig2_network": experiments.head_ablation(tr0.blob, rounds=0)}
+    # the same comparison over several regimes (well to under-resolved), each
+    # trained on its own data, with Eq. 4 and with the ghost moments of the
+    # residual down-weighted
+    regs = experiments.fixed_error_regimes()
+    out["fixed_error_regimes"] = [
+        {"regime": r["regime"], "n_coarse": r["n_coarse"],
+         "bgk_error_at_end": {k: float(f"{v[-1]:.3g}") for k, v in r["bgk_errors"].items()},
+         "runs": [{"network": u["network"], "ghost_weight": u["ghost_weight"],
+                   "heldout_loss_over_bgk": round(u["heldout_loss_over_bgk"], 3),
+                   "error_at_end": float(f"{u['gnn_errors'][-1]:.3g}"),
+                   "bgk_lattice_at_gnn_error": u["bgk_lattice_at_gnn_error"]}
+                  for u in r["runs"]]} for r in regs]
     # the long high-Re rollout with both trained networks and plain BGK,
     # against the FP64 oracle's stored energies of the same flow
     out["long_rollout_2048_re1e4"] = long_rollout_leg({2: tr.blob, 0: tr0.blob})

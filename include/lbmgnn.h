@@ -313,6 +313,19 @@ int gnn_mse(const float *a, const float *b, int batch, int nx, int ny,
             double scale, double *loss, float *grad_a, void *workspace,
             size_t ws_bytes, void *stream);
 
+/* Eq. 4 with the per-node residual r = a - b (nine populations) weighted by
+ * a symmetric 9 x 9 matrix Q: loss = scale/N * sum over nodes of r^T Q r,
+ * grad_a = 2 scale/N * Q r.  Q = identity is gnn_mse; Q = M^T W M with M a
+ * moment basis of D2Q9 and W diagonal weights the residual's moments (a
+ * training option beside the paper's plain Eq. 4, used to weight the
+ * hydrodynamic moments over the non-hydrodynamic ones).  a, b, grad_a in the
+ * row-interleaved layout [batch][ny][9][nx]; q: host, 81 doubles, row-major,
+ * must be finite and symmetric (LBM_EINVAL otherwise); products with Q in
+ * FP64.  workspace: >= lbm_workspace_bytes(LBM_WS_MSE, batch, nx, ny, 0). */
+int gnn_mse_weighted(const float *a, const float *b, int batch, int nx, int ny,
+                     const double *q, double scale, double *loss, float *grad_a,
+                     void *workspace, size_t ws_bytes, void *stream);
+
 /* One Adam step (Kingma and Ba) on n FP32 parameters with FP32 moments m, v
  * (zero before the first step); step is the 1-based count after this one. */
 int gnn_adam(float *params, const float *grad, float *m, float *v, size_t n,

@@ -93,6 +93,8 @@ def lib():
         L.orc_gnn_collide_gated.restype = i
         L.orc_mse.argtypes = [pd, pd, sz]
         L.orc_mse.restype = d
+        L.orc_mse_weighted.argtypes = [pd, pd, sz, pd]
+        L.orc_mse_weighted.restype = d
         L.orc_adam.argtypes = [pd, pd, pd, pd, sz, d, d, d, d, i]
         _lib = L
     return _lib
@@ -355,6 +357,14 @@ def mse(a, b) -> float:
     a = _f64(np.moveaxis(np.asarray(a), -3, -1))
     b = _f64(np.moveaxis(np.asarray(b), -3, -1))
     return lib().orc_mse(_p(a), _p(b), a.size // 9)
+
+
+def mse_weighted(a, b, q) -> float:
+    """Eq. 4 with each node's residual weighted by the 9 x 9 matrix q;
+    a, b shaped [..., 9, ny, nx]."""
+    a = _f64(np.moveaxis(np.asarray(a), -3, -1))
+    b = _f64(np.moveaxis(np.asarray(b), -3, -1))
+    return lib().orc_mse_weighted(_p(a), _p(b), a.size // 9, _p(_f64(q)))
 
 
 def adam(p, g, m, v, lr, beta1, beta2, eps, step):

@@ -668,6 +668,19 @@ double orc_mse(const double *a, const double *b, size_t nodes) {
   return s / (double)nodes;
 }
 
+/* Eq. 4 with each node's residual r = a - b weighted by a 9 x 9 matrix Q:
+ * (1/N) sum_nodes r^T Q r.  Q = identity gives orc_mse.  a, b: [nodes][9]. */
+double orc_mse_weighted(const double *a, const double *b, size_t nodes, const double *q) {
+  double s = 0.0;
+  for (size_t n = 0; n < nodes; ++n) {
+    double r[9];
+    for (int i = 0; i < 9; ++i) r[i] = a[9 * n + i] - b[9 * n + i];
+    for (int i = 0; i < 9; ++i)
+      for (int j = 0; j < 9; ++j) s += r[i] * q[9 * i + j] * r[j];
+  }
+  return s / (double)nodes;
+}
+
 /* One Adam step (Kingma and Ba, Algorithm 1) with bias correction;
  * step is the 1-based step count after this update. */
 void orc_adam(double *p, const double *g, double *m, double *v, size_t n,

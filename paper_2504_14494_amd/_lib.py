@@ -26,7 +26,8 @@ EXPORTS = [
     "lbm_stream", "lbm_init_ce", "lbm_init_ce_f64",
     "lbm_step_channel", "lbm_step_channel_f64", "lbm_channel_profile",
     "lbm_moments", "lbm_restrict", "lbm_copy", "gnn_param_count", "gnn_blob_len",
-    "lbm_step_gnn", "lbm_step_gnn_noalloc", "gnn_forward", "gnn_backward", "gnn_mse", "gnn_adam",
+    "lbm_step_gnn", "lbm_step_gnn_noalloc", "gnn_forward", "gnn_backward", "gnn_mse",
+    "gnn_mse_weighted", "gnn_adam",
     "lbm_step_simple", "lbm_step_simple_channel", "simple_forward", "gnn_gelu_rate",
     "lbm_workspace_bytes",
 ]
@@ -84,6 +85,8 @@ def load(path: str = LIB_PATH):
         "gnn_forward": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp, sz, vp], i),
         "gnn_backward": ([vp, vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
         "gnn_mse": ([vp, vp, i, i, i, d, vp, vp, vp, sz, vp], i),
+        "gnn_mse_weighted": ([vp, vp, i, i, i, ctypes.POINTER(ctypes.c_double), d, vp, vp, vp,
+                              sz, vp], i),
         "gnn_adam": ([vp, vp, vp, vp, sz, f, f, f, f, i, vp], i),
         "lbm_step_simple": ([vp, vp, i, i, f, vp, ctypes.POINTER(LbmFallback), vp, sz, vp], i),
         "lbm_step_simple_channel": ([vp, vp, i, i, f, f, vp, ctypes.POINTER(LbmFallback), vp, sz,

@@ -904,6 +904,48 @@ __global__ __launch_bounds__(kBT) void mse_kernel(const float *__restrict__ a,
   if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
 }
 
+// Eq. 4 with the residual weighted by a symmetric 9 x 9 matrix Q per node:
+// sum over nodes of r^T Q r, r = a - b over the nine populations of a node
+// (row-interleaved layout [batch][ny][9][nx]); gradient gscale * Q r.  The
+// products with Q are taken in FP64.
+struct MseWeights {
+  double q[81];
+};
+
+__global__ __launch_bounds__(kBT) void mse_weighted_kernel(const float *__restrict__ a,
+                                                           const float *__restrict__ b,
+                                                           int batch, int nx, int ny,
+                                                           MseWeights Q, float gscale,
+                                                           float *__restrict__ grad,
+                                                           double *__restrict__ partials) {
+  __shared__ double sm[kBT];
+  double s = 0.0;
+  const size_t nodes = (size_t)batch * ny * nx;
+  for (size_t k = (size_t)blockIdx.x * kBT + threadIdx.x; k < nodes;
+       k += (size_t)gridDim.x * kBT) {
+    const size_t row = k / (size_t)nx, x = k - row * nx;     // row = b * ny + y
+    const size_t base = row * 9 * (size_t)nx + x;
+    double r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = (double)a[base + (size_t)i * nx] - (double)b[base + (size_t)i * nx];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) t += Q.q[9 * i + j] * r[j];
+      s += r[i] * t;
+      if (grad) grad[base + (size_t)i * nx] = gscale * (float)t;
+    }
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = kBT / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+}
+
 __global__ __launch_bounds__(kBT) void mse_finalize(const double *__restrict__ partials, int nb,
                                                     double scale, double *__restrict__ loss) {
   __shared__ double sm[kBT];
@@ -1027,6 +1069,35 @@ extern "C" int gnn_mse(const float *a, const float *b, int batch, int nx, int ny
   hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(kBT), 0, s, a, b, n,
                      (float)(2.0 * scale / (double)nodes), grad_a, (double *)workspace);
   if (int rc = launch_check("mse_kernel")) return rc;
+  hipLaunchKernelGGL(mse_finalize, dim3(1), dim3(kBT), 0, s, (const double *)workspace, nb,
+                     scale / (double)nodes, loss);
+  return launch_check("mse_finalize");
+}
+
+extern "C" int gnn_mse_weighted(const float *a, const float *b, int batch, int nx, int ny,
+                                const double *q, double scale, double *loss, float *grad_a,
+                                void *workspace, size_t ws_bytes, void *stream) {
+  if (!a || !b || !loss || !q) return fail(LBM_EINVAL, "gnn_mse_weighted: null pointer");
+  if (batch < 1 || !lbm::lattice_ok(nx, ny) || (long long)batch * nx * ny >= (1LL << 31))
+    return fail(LBM_EINVAL, "gnn_mse_weighted: bad sizes");
+  MseWeights Q;
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      const double v = q[9 * i + j];
+      if (!(fabs(v) < INFINITY) || v != q[9 * j + i])
+        return fail(LBM_EINVAL, "gnn_mse_weighted: Q must be finite and symmetric");
+      Q.q[9 * i + j] = v;
+    }
+  const long long nodes = (long long)batch * nx * ny;
+  const int nb = lbm::reduce_blocks(nodes);
+  if (!workspace || ws_bytes < (size_t)nb * 8 * sizeof(double))
+    return fail(LBM_EWORKSPACE, "gnn_mse_weighted: workspace needs %zu bytes",
+                (size_t)nb * 8 * sizeof(double));
+  if (int rc = check_device()) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(mse_weighted_kernel, dim3(nb), dim3(kBT), 0, s, a, b, batch, nx, ny, Q,
+                     (float)(2.0 * scale / (double)nodes), grad_a, (double *)workspace);
+  if (int rc = launch_check("mse_weighted_kernel")) return rc;
   hipLaunchKernelGGL(mse_finalize, dim3(1), dim3(kBT), 0, s, (const double *)workspace, nb,
                      scale / (double)nodes, loss);
   return launch_check("mse_finalize");

@@ -86,11 +86,18 @@ def coarse_run(n, u0, re, phase, steps_list, blob=None, rounds=2):
 
 
 def fixed_error_report(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_fine=512,
-                       n_gnn=128, bgk_sizes=(128, 256), coarse_steps=(250, 500, 1000),
+                       n_gnn=128, bgk_sizes=(16, 32, 64, 128, 256), coarse_steps=(256, 512, 1024),
                        mlups_bgk=None, mlups_gnn=None):
-    """Velocity errors of the trained GNN at n_gnn and of BGK on bgk_sizes
-    against the restricted FP64 reference, and the time each needs to reach
-    the last time, projected from the large-lattice MLUPS when given."""
+    """Velocity errors of the trained GNN at n_gnn and of BGK on a ladder of
+    lattices (coarser and finer than n_gnn) against the restricted FP64
+    reference, the smallest BGK lattice at least as accurate as the GNN at
+    the last time, and the time each needs to reach it, projected from the
+    large-lattice MLUPS when given.  Every lattice of the ladder divides
+    n_fine, and its step counts m * n / n_gnn are whole, so that all runs are
+    compared at the same physical times."""
+    for n in bgk_sizes:
+        if n_fine % n or any(m * n % n_gnn for m in coarse_steps):
+            raise ValueError(f"lattice {n} does not divide the fine lattice or the step counts")
     sizes = sorted(set(bgk_sizes) | {n_gnn})
     times = sorted({m * (n_fine // n_gnn) for m in coarse_steps})
     ref = fine_reference(u0, re, phase, n_fine, sizes, times)
@@ -120,6 +127,57 @@ def fixed_error_report(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_
             proj[f"bgk_{n}"] = n * n * (last * n // n_gnn) / (mlups_bgk * 1e6)
         rep["projected_seconds_at_large_lattice_mlups"] = proj
     return rep
+
+
+# Regimes of the fixed-error comparison: (name, fine lattice, coarsening
+# factor, training Reynolds-number range, test Reynolds number, coarse steps
+# of the test window, BGK ladder).  Acoustic scaling throughout (u0 in
+# [0.02, 0.06] for training, 0.04 for the test); from a well resolved vortex
+# (128^2) to one resolved by 16 nodes, where plain BGK is 1e-3 off.
+FIXED_ERROR_REGIMES = (
+    ("128_from_512_re2000", 512, 4, (1000.0, 5000.0), 2000.0, (256, 512, 1024),
+     (16, 32, 64, 128, 256)),
+    ("32_from_128_re2000", 128, 4, (1000.0, 5000.0), 2000.0, (64, 128, 256), (8, 16, 32, 64)),
+    ("32_from_128_re200", 128, 4, (100.0, 500.0), 200.0, (64, 128, 256), (8, 16, 32, 64)),
+    ("32_from_256_re200", 256, 8, (100.0, 500.0), 200.0, (64, 128, 256), (8, 16, 32, 64, 128)),
+    ("16_from_128_re100", 128, 8, (50.0, 250.0), 100.0, (32, 64, 128), (8, 16, 32, 64)),
+)
+
+
+def fixed_error_regimes(regimes=FIXED_ERROR_REGIMES, ghost_weights=(1.0, 1e-2),
+                        rounds_list=(2, 0)):
+    """The fixed-error comparison over several regimes.  For each regime the
+    training pairs are generated on its own lattices (fine n_fine, coarse
+    n_fine / factor, training Reynolds range), both networks are trained on
+    Eq. 4 (ghost weight 1) and with the residual's non-hydrodynamic moments
+    down-weighted (train.moment_weighted_q), and each trained network's
+    rollout error at the coarse lattice is set against BGK on the ladder."""
+    from . import train
+    out = []
+    for name, nf, fac, rer, re, steps, ladder in regimes:
+        nc = nf // fac
+        cfg = train.DataConfig(n_fine=nf, factor=fac, re_range=rer, coarse_steps=steps[-1])
+        data = train.datasets(cfg)
+        row = {"regime": name, "n_coarse": nc, "n_fine": nf, "re": re,
+               "coarse_steps": list(steps), "runs": []}
+        bgk = None
+        for wg in ghost_weights:
+            q = None if wg == 1.0 else train.moment_weighted_q(wg)
+            for rounds in rounds_list:
+                tr, rep = train.train(cfg, steps=2000, batch=32, rounds=rounds, data=data, loss_q=q)
+                fe = fixed_error_report(tr.blob, rounds=rounds, re=re, n_fine=nf, n_gnn=nc,
+                                        bgk_sizes=ladder, coarse_steps=steps)
+                if bgk is None:
+                    bgk = {k: v for k, v in fe["errors"].items() if k.startswith("bgk_")}
+                row["runs"].append({
+                    "network": "message-passing" if rounds else "fig2", "ghost_weight": wg,
+                    "heldout_loss_over_bgk": rep["heldout_rel_loss_after"],
+                    "gnn_errors": fe["errors"][f"gnn_{nc}"],
+                    "fallback_steps": fe["fallback_steps"],
+                    "bgk_lattice_at_gnn_error": fe["bgk_lattice_at_gnn_error"]})
+        row["bgk_errors"] = bgk
+        out.append(row)
+    return out
 
 
 def head_ablation(blob, rounds=2, u0=0.04, re=2000.0, phase=(0.25, 0.4), n_fine=512,
@@ -477,8 +535,9 @@ def poiseuille_refinement(heights=(16, 32, 64), re=100.0, u_max=0.05, fp64=False
 
 def main(argv=None):
     """Runs one study and prints its report as JSON:
-    python -m paper_2504_14494_amd.experiments {fixed-error, resolution,
-    stability, poiseuille, poiseuille-refinement, long-rollout, tgv-validation}
+    python -m paper_2504_14494_amd.experiments {fixed-error, fixed-error-regimes,
+    resolution, stability, poiseuille, poiseuille-refinement, long-rollout,
+    tgv-validation}
     [--rounds R].  The corrected-collision
     studies first train the network (train.train, full configuration); the
     Poiseuille study runs a network only with --rounds 0 (the per-node
@@ -490,8 +549,9 @@ def main(argv=None):
 
     from . import train
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["fixed-error", "resolution", "stability", "poiseuille",
-                                      "poiseuille-refinement", "long-rollout", "tgv-validation"])
+    ap.add_argument("study", choices=["fixed-error", "fixed-error-regimes", "resolution",
+                                      "stability", "poiseuille", "poiseuille-refinement",
+                                      "long-rollout", "tgv-validation"])
     ap.add_argument("--rounds", type=int, default=2, help="2: message passing; 0: Fig. 2")
     ap.add_argument("--scaling", default="diffusive", choices=["diffusive", "acoustic"])
     ap.add_argument("--fp64", action="store_true", help="BGK runs in FP64 (resolution, poiseuille)")
@@ -510,6 +570,8 @@ def main(argv=None):
         blob = tr.blob
     if args.study == "fixed-error":
         out = fixed_error_report(blob, rounds=args.rounds)
+    elif args.study == "fixed-error-regimes":
+        out = {"regimes": fixed_error_regimes()}
     elif args.study == "resolution":
         out = {"bgk": resolution_study(None, scaling=args.scaling, fp64=args.fp64)}
         if blob is not None:

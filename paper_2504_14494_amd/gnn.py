@@ -18,7 +18,7 @@ from .lbm import Lattice, Workspace, _need, _ptr, _stream, lbm_moments
 __all__ = ["gnn_param_count", "gnn_blob_len", "saved_bytes", "gnn_forward", "lbm_step_gnn",
            "lbm_step_gnn_noalloc",
            "Fallback", "GnnLattice", "gnn_backward", "gnn_mse", "gnn_adam", "GnnCollide",
-           "GnnMse", "simple_forward", "lbm_step_simple", "lbm_step_simple_channel",
+           "GnnMse", "gnn_mse_weighted", "simple_forward", "lbm_step_simple", "lbm_step_simple_channel",
            "gnn_gelu_rate", "collide"]
 
 
@@ -361,6 +361,28 @@ def gnn_mse(a: torch.Tensor, b: torch.Tensor, scale: float = 1.0, want_grad: boo
     rc = L.gnn_mse(_ptr(a), _ptr(b), 1, nodes, 1, float(scale), _ptr(loss), _ptr(grad),
                    _ptr(buf), buf.numel(), _stream())
     check(rc, "gnn_mse")
+    return loss, grad
+
+
+def gnn_mse_weighted(a: torch.Tensor, b: torch.Tensor, q, scale: float = 1.0,
+                     want_grad: bool = True, ws: Workspace = None):
+    """Eq. 4 with each node's residual weighted by the symmetric 9 x 9 matrix
+    q (host array-like): scale / N * sum over nodes of r^T q r.  a, b:
+    populations [ny, 9, nx] or [batch, ny, 9, nx].  Returns (loss as a
+    device float64 [1], dloss/da or None)."""
+    _need(a, torch.float32, "a")
+    _need(b, torch.float32, "b")
+    if a.shape != b.shape:
+        raise ValueError("a and b must be populations of the same shape")
+    B, nx, ny = _batch_dims(a if a.dim() == 4 else a.unsqueeze(0))
+    qd = (ctypes.c_double * 81)(*[float(v) for row in q for v in row])
+    loss = torch.empty(1, dtype=torch.float64, device=a.device)
+    grad = torch.empty_like(a) if want_grad else None
+    L = _lib.load()
+    buf = (ws or _ws).get(L.lbm_workspace_bytes(_lib.LBM_WS_MSE, B, nx, ny, 0))
+    rc = L.gnn_mse_weighted(_ptr(a), _ptr(b), B, nx, ny, qd, float(scale), _ptr(loss),
+                            _ptr(grad), _ptr(buf), buf.numel(), _stream())
+    check(rc, "gnn_mse_weighted")
     return loss, grad
 
 

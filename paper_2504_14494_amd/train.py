@@ -131,6 +131,42 @@ def make_dataset(cfg: DataConfig, device="cuda"):
             torch.tensor(T, dtype=torch.float32, device=device))
 
 
+# An orthogonal moment basis of D2Q9 (rows over the directions 0:(0,0)
+# 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)):
+# density, energy, energy square, x- and y-momentum, the two energy fluxes,
+# and the two shear stresses.  The density and momentum rows are conserved by
+# the corrected collision; energy and the stresses are hydrodynamic; the
+# energy square and the fluxes are non-hydrodynamic ("ghost") moments.
+MOMENT_BASIS = np.array([
+    [1, 1, 1, 1, 1, 1, 1, 1, 1],
+    [-4, -1, -1, -1, -1, 2, 2, 2, 2],
+    [4, -2, -2, -2, -2, 1, 1, 1, 1],
+    [0, 1, 0, -1, 0, 1, -1, -1, 1],
+    [0, -2, 0, 2, 0, 1, -1, -1, 1],
+    [0, 0, 1, 0, -1, 1, 1, -1, -1],
+    [0, 0, -2, 0, 2, 1, 1, -1, -1],
+    [0, 1, -1, 1, -1, 0, 0, 0, 0],
+    [0, 0, 0, 0, 0, 1, -1, 1, -1]], dtype=np.float64)
+GHOST_MOMENTS = (2, 4, 6)
+
+
+def moment_weighted_q(w_ghost: float) -> np.ndarray:
+    """9 x 9 weight matrix of the residual for gnn_mse_weighted: the residual
+    is taken to the orthonormal moment basis, its ghost moments are scaled
+    by w_ghost, the others by 1.  w_ghost = 1 gives the identity (Eq. 4)."""
+    mh = MOMENT_BASIS / np.linalg.norm(MOMENT_BASIS, axis=1, keepdims=True)
+    w = np.ones(9)
+    w[list(GHOST_MOMENTS)] = w_ghost
+    q = mh.T @ np.diag(w) @ mh
+    return 0.5 * (q + q.T)              # exactly symmetric, as gnn_mse_weighted requires
+
+
+def _loss(out, y, scale, loss_q, want_grad):
+    if loss_q is None:
+        return gnn.gnn_mse(out, y, scale, want_grad=want_grad)
+    return gnn.gnn_mse_weighted(out, y, loss_q, scale, want_grad=want_grad)
+
+
 def zero_head(blob: torch.Tensor, rounds: int) -> torch.Tensor:
     """The same network with W_h = 0, b_h = 0: the plain BGK collision."""
     off = inputs.blob_offsets(rounds)
@@ -140,24 +176,25 @@ def zero_head(blob: torch.Tensor, rounds: int) -> torch.Tensor:
     return b
 
 
-def bgk_loss(X, Y, T, rounds: int, chunk: int = 32) -> float:
-    """Eq. 4 of the plain BGK collision over a whole set (scale 1)."""
+def bgk_loss(X, Y, T, rounds: int, chunk: int = 32, loss_q=None) -> float:
+    """Eq. 4 (or its moment-weighted form) of the plain BGK collision over a
+    whole set (scale 1)."""
     blob = zero_head(torch.as_tensor(inputs.gnn_blob(0, rounds), device=X.device), rounds)
     total, nodes = 0.0, 0
     for s in range(0, X.shape[0], chunk):
         out, _ = gnn.collide(X[s:s + chunk], T[s:s + chunk], blob, rounds)
-        loss, _ = gnn.gnn_mse(out, Y[s:s + chunk], 1.0, want_grad=False)
+        loss, _ = _loss(out, Y[s:s + chunk], 1.0, loss_q, False)
         n = out.numel() // 9
         total += loss.item() * n
         nodes += n
     return total / nodes
 
 
-def eval_loss(blob, X, Y, T, rounds: int, scale: float, chunk: int = 32) -> float:
+def eval_loss(blob, X, Y, T, rounds: int, scale: float, chunk: int = 32, loss_q=None) -> float:
     total, nodes = 0.0, 0
     for s in range(0, X.shape[0], chunk):
         out, _ = gnn.collide(X[s:s + chunk], T[s:s + chunk], blob, rounds)
-        loss, _ = gnn.gnn_mse(out, Y[s:s + chunk], scale, want_grad=False)
+        loss, _ = _loss(out, Y[s:s + chunk], scale, loss_q, False)
         n = out.numel() // 9
         total += loss.item() * n
         nodes += n
@@ -169,9 +206,10 @@ class Trainer:
     loss and update kernels."""
 
     def __init__(self, blob: torch.Tensor, rounds: int = 2, lr: float = 1e-3,
-                 betas=(0.9, 0.999), eps: float = 1e-8, shuffle_seed: int = 0):
+                 betas=(0.9, 0.999), eps: float = 1e-8, shuffle_seed: int = 0, loss_q=None):
         self.blob = blob.contiguous()
         self.rounds = rounds
+        self.loss_q = loss_q      # None: Eq. 4; else the 9 x 9 residual weight matrix
         self.lr, self.betas, self.eps = lr, betas, eps
         n = gnn.gnn_param_count(rounds)
         self.m = torch.zeros(n, dtype=torch.float32, device=blob.device)
@@ -196,7 +234,7 @@ class Trainer:
         saved = torch.empty(gnn.saved_bytes(B, nx, ny, self.rounds), dtype=torch.uint8,
                             device=xb.device)
         out, _ = gnn.collide(xb, tb, self.blob, self.rounds, saved=saved)
-        loss, dl = gnn.gnn_mse(out, yb, scale)
+        loss, dl = _loss(out, yb, scale, self.loss_q, True)
         grad = gnn.gnn_backward(dl, xb, saved, tb, self.blob, self.rounds)
         self.step_count += 1
         gnn.gnn_adam(self.blob, grad, self.m, self.v, self.step_count, self.lr, self.betas[0],
@@ -237,10 +275,12 @@ def datasets(cfg: DataConfig = None, held_out_runs: int = 8, device="cuda"):
 
 def train(cfg: DataConfig = None, steps: int = 2000, batch: int = 32, rounds: int = 2,
           lr: float = 1e-3, init_seed: int = 0, s_delta: float = 1e-4, held_out_runs: int = 8,
-          log_every: int = 0, device="cuda", data=None):
+          log_every: int = 0, device="cuda", data=None, loss_q=None):
     """Full training run; returns (trainer, report dict).  `data` reuses the
     pairs of datasets() (same cfg and held_out_runs) instead of generating
-    them."""
+    them.  loss_q: None trains on Eq. 4; a 9 x 9 matrix (moment_weighted_q)
+    weights each node's residual, the loss then relative to the same
+    weighted loss of plain BGK."""
     import time
     t0 = time.perf_counter()
     if data is None:
@@ -248,11 +288,11 @@ def train(cfg: DataConfig = None, steps: int = 2000, batch: int = 32, rounds: in
     (X, Y, T), (Xh, Yh, Th) = data
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    l_bgk = bgk_loss(X, Y, T, rounds)
-    l_bgk_h = bgk_loss(Xh, Yh, Th, rounds)
+    l_bgk = bgk_loss(X, Y, T, rounds, loss_q=loss_q)
+    l_bgk_h = bgk_loss(Xh, Yh, Th, rounds, loss_q=loss_q)
     blob = torch.as_tensor(inputs.gnn_blob(init_seed, rounds, s_delta=s_delta), device=device)
-    tr = Trainer(blob, rounds, lr)
-    before = eval_loss(tr.blob, Xh, Yh, Th, rounds, 1.0 / l_bgk_h)
+    tr = Trainer(blob, rounds, lr, loss_q=loss_q)
+    before = eval_loss(tr.blob, Xh, Yh, Th, rounds, 1.0 / l_bgk_h, loss_q=loss_q)
     hist = []
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -262,8 +302,8 @@ def train(cfg: DataConfig = None, steps: int = 2000, batch: int = 32, rounds: in
             hist.append((k, loss.item()))
     torch.cuda.synchronize()
     t_opt = time.perf_counter() - t1
-    after = eval_loss(tr.blob, Xh, Yh, Th, rounds, 1.0 / l_bgk_h)
-    train_after = eval_loss(tr.blob, X, Y, T, rounds, 1.0 / l_bgk)
+    after = eval_loss(tr.blob, Xh, Yh, Th, rounds, 1.0 / l_bgk_h, loss_q=loss_q)
+    train_after = eval_loss(tr.blob, X, Y, T, rounds, 1.0 / l_bgk, loss_q=loss_q)
     return tr, {"bgk_loss_train": l_bgk, "bgk_loss_heldout": l_bgk_h,
                 "heldout_rel_loss_before": before, "heldout_rel_loss_after": after,
                 "train_rel_loss_after": train_after, "history": hist,

@@ -118,6 +118,35 @@ def test_mse_is_eq4(orc):
     assert np.abs(grad.double().cpu().numpy() - gref).max() <= 1e-6 * np.abs(gref).max()
 
 
+def test_moment_weighted_loss_matches_oracle(orc):
+    """The moment-weighted form of Eq. 4 (training option): loss against the
+    oracle's, on the row-interleaved layout with a ragged width; the gradient
+    against central differences of the oracle's loss along random
+    directions, and with the identity weight equal to gnn_mse's."""
+    from paper_2504_14494_amd import train
+    a = inputs.random_shifted_state((2, 7, 9, 13), 4e-3, seed=15)
+    b = inputs.random_shifted_state((2, 7, 9, 13), 4e-3, seed=16)
+    q = train.moment_weighted_q(1e-2)
+    loss, grad = gnn.gnn_mse_weighted(_dev(a), _dev(b), q, scale=3.0)
+    ap, bp = (inputs.rows_to_planes(t.astype(np.float64)) for t in (a, b))
+    ref = 3.0 * orc.mse_weighted(ap, bp, q)
+    assert abs(loss.item() - ref) / ref < 1e-9
+    g = inputs.rows_to_planes(grad.double().cpu().numpy())
+    rng = np.random.default_rng(17)
+    for _ in range(3):
+        v = rng.standard_normal(ap.shape)
+        eps = 1e-4
+        fd = 3.0 * (orc.mse_weighted(ap + eps * v, bp, q) - orc.mse_weighted(ap - eps * v, bp, q))
+        fd /= 2 * eps
+        assert abs(fd - float((g * v).sum())) <= 1e-5 * abs(fd)
+    # identity weight: gnn_mse's loss (which squares the FP32-rounded
+    # residual, hence 1e-6, its own bar) and its gradient value for value
+    l_i, g_i = gnn.gnn_mse_weighted(_dev(a), _dev(b), np.eye(9), scale=3.0)
+    l_p, g_p = gnn.gnn_mse(_dev(a), _dev(b), scale=3.0)
+    assert abs(l_i.item() - l_p.item()) <= 1e-6 * l_p.item()
+    assert torch.equal(g_i, g_p)
+
+
 def test_adam_matches_oracle(orc):
     rng = np.random.default_rng(7)
     n = 5000

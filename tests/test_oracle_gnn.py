@@ -390,6 +390,44 @@ def test_mse_is_eq4(orc):
     assert abs(orc.mse(a, b) - ((a - b) ** 2).sum() / (3 * 4 * 5)) < 1e-12
 
 
+def test_moment_weighted_mse(orc):
+    """The weighted form of Eq. 4 (a training option): the identity weight
+    gives Eq. 4; a rank-one weight v v^T gives the mean over nodes of
+    (v . r)^2 (an elementary identity, computed here by brute force over the
+    nodes); the weight is linear in Q."""
+    rng = np.random.default_rng(26)
+    a = rng.standard_normal((2, 9, 3, 4))
+    b = rng.standard_normal((2, 9, 3, 4))
+    assert abs(orc.mse_weighted(a, b, np.eye(9)) - orc.mse(a, b)) < 1e-13
+    v = rng.standard_normal(9)
+    r = a - b
+    brute = np.mean([float(v @ r[k, :, y, x]) ** 2 for k in range(2) for y in range(3)
+                     for x in range(4)])
+    assert abs(orc.mse_weighted(a, b, np.outer(v, v)) - brute) < 1e-12 * brute
+    q1, q2 = np.eye(9), np.outer(v, v)
+    assert abs(orc.mse_weighted(a, b, 2 * q1 + 3 * q2)
+               - 2 * orc.mse_weighted(a, b, q1) - 3 * orc.mse_weighted(a, b, q2)) < 1e-11
+
+
+def test_moment_weight_matrix_of_the_training_option():
+    """The D2Q9 moment basis used to weight the loss is orthogonal, the
+    weight matrix with unit weights is the identity (plain Eq. 4) and it is
+    exactly symmetric; with small ghost weights it leaves the hydrodynamic
+    moments' residual unchanged and shrinks the ghost moments'."""
+    from paper_2504_14494_amd import train
+    M = train.MOMENT_BASIS
+    G = M @ M.T
+    assert np.abs(G - np.diag(np.diag(G))).max() == 0
+    assert np.abs(train.moment_weighted_q(1.0) - np.eye(9)).max() < 1e-15
+    q = train.moment_weighted_q(1e-2)
+    assert np.array_equal(q, q.T)
+    mh = M / np.linalg.norm(M, axis=1, keepdims=True)
+    for k in range(9):
+        r = mh[k]
+        expect = 1e-2 if k in train.GHOST_MOMENTS else 1.0
+        assert abs(r @ q @ r - expect) < 1e-14
+
+
 def test_adam_matches_torch(orc):
     rng = np.random.default_rng(17)
     p = rng.standard_normal(50)
