@@ -203,10 +203,22 @@ def gnn_roofline(ms_per_step, nodes, gelu_measured=None):
     if gelu_measured:
         alu["gelu_ceiling_measured"] = round(gelu_measured / 1e12, 3)
         alu["frac_of_measured"] = round(gelu_rate / gelu_measured, 4)
+    # The SIMD issues MFMA and VALU work of a wave one after the other (the
+    # counters of the round kernels add up to ~97 % busy), so the step's
+    # ceiling is the serialised issue time of its algorithmic work: per node
+    # 1,280 GELUs at 9 slots (16 lanes per cycle) plus the minimum MFMA work
+    # at 1,017 FLOP per SIMD cycle; peak 1024 SIMDs x 2.4 GHz.
+    simd_cycles = GNN_GELU_PER_NODE * GELU_SLOTS / 16.0 + \
+        2.0 * GNN_MAC_PER_NODE / (MFMA_BF16_PEAK_TFLOPS * 1e12 / (1024 * 2.4e9))
+    issue = simd_cycles * nodes / sec / 1e9
     r = {"roofline_mfma": {"bound": "mfma", "achieved": round(mfma_tf, 1),
                            "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(mfma_tf / MFMA_BF16_PEAK_TFLOPS, 4)},
-         "roofline_alu": alu}
+         "roofline_alu": alu,
+         "roofline_issue": {"bound": "alu", "achieved": round(issue, 1),
+                            "peak": 1024 * 2.4, "unit": "G SIMD issue cycles/s",
+                            "frac": round(issue / (1024 * 2.4), 4),
+                            "simd_cycles_per_node": round(simd_cycles, 1)}}
     t = _committed(GNN_PMC_FILE, gnn_src_hash())
     r["counters"] = None if t is None else t.get("utilisation")
     return r
