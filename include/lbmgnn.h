@@ -125,7 +125,10 @@ int lbm_moments(const float *g, int nx, int ny, float *rho, float *ux,
                 float *uy, const lbm_tgv *analytic, double *sums,
                 void *workspace, size_t ws_bytes, void *stream);
 
-/* Restriction of a fine FP64 run onto a coarse FP32 lattice (training data).
+/* Restriction of a fine FP64 run onto a coarse FP32 lattice: the training
+ * pairs of Methodology, "Training Methodology" (coarse states regressed
+ * toward high-resolution runs; the paper names no restriction, this is the
+ * reading taken).
  * g_fine [nyf][9][nxf] FP64 shifted; if `pull` is set it is read through one
  * streaming step (a post-collision state becomes the next pre-collision one),
  * else it is taken as a pre-collision state.  Coarse node X sits on fine node
@@ -169,7 +172,8 @@ int lbm_channel_profile(const float *g, int nx, int ny, float gx, double *prof,
 /* Plain copy of n floats (bandwidth reference for the BGK kernel). */
 int lbm_copy(const float *src, float *dst, size_t n, void *stream);
 
-/* VALU throughput reference for the corrected step: each of nblocks x 256
+/* VALU throughput reference for the corrected step (the GELU of "GNN
+ * Architecture Details", tanh form): each of nblocks x 256
  * threads applies the network's GELU (tanh form, evaluated as
  * x / (1 + 2^(x (A + B x^2)))) `iters` times to eight independent register
  * values and writes their sum to out[thread].  `out` is a device array of
@@ -326,7 +330,9 @@ int gnn_mse_weighted(const float *a, const float *b, int batch, int nx, int ny,
                      const double *q, double scale, double *loss, float *grad_a,
                      void *workspace, size_t ws_bytes, void *stream);
 
-/* One Adam step (Kingma and Ba) on n FP32 parameters with FP32 moments m, v
+/* One optimiser step of the training loop (Methodology, "Training
+ * Methodology"; the paper names no optimiser: Adam, Kingma and Ba, Algorithm
+ * 1) on n FP32 parameters with FP32 moments m, v
  * (zero before the first step); step is the 1-based count after this one. */
 int gnn_adam(float *params, const float *grad, float *m, float *v, size_t n,
              float lr, float beta1, float beta2, float eps, int step,

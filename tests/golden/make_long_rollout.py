@@ -16,7 +16,7 @@ Everything is computed by oracle/ (FP64); numpy only slices and sums its
 outputs.  The oracle's loops share their nodes among OMP threads, which does
 not change any value.  Takes about 35 minutes on 8 cores.
 
-    python tests/golden/make_cfg5.py [--threads 8]
+    python tests/golden/make_long_rollout.py [--threads 8]
 """
 from __future__ import annotations
 
@@ -81,7 +81,7 @@ def main(argv=None):
         f"energy_256: 1/2 sum |u|^2 over the injection of every {STRIDE}th node (256 x 256); "
         "mass: sum f over the whole lattice",
         "ux/uy: velocity at the sampled nodes (y, x) " + " ".join(f"{y},{x}" for y, x in NODES),
-        "written by tests/golden/make_cfg5.py (calls oracle/ only)",
+        "written by tests/golden/make_long_rollout.py (calls oracle/ only)",
         "columns: step energy_256 mass " + " ".join(f"ux{k} uy{k}" for k in range(len(NODES))),
     ]
     tmp = OUT + ".tmp"

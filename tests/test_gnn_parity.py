@@ -3,9 +3,9 @@ enhancement and its integration with the LBM, Eq. 3) against the CPU oracle.
 
 The library computes the network in BF16 with FP32 accumulation.  It is
 compared with the oracle in two modes:
-  mode 0  FP64 throughout: the spec bar (corrected populations within
-          1e-3 relative at the inference workload's correction scale
-          s_delta = 1e-4) and a bound on the correction itself;
+  mode 0  FP64 throughout: corrected populations within 1e-3 relative at
+          the inference workload's correction scale s_delta = 1e-4, and a
+          bound on the correction itself;
   mode 1  FP64 arithmetic with BF16 rounding at the points where the kernel
           stores BF16 (weights, features, activations, summed messages):
           head outputs agree to summation-order effects only.

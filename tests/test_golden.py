@@ -74,7 +74,7 @@ def test_golden_tgv_fp32_library():
 
 
 # ------------------------------------------- long high-Re rollout reference ---
-# tests/golden/tgv2048_re1e4_energy.txt, written by make_cfg5.py from the FP64
+# tests/golden/tgv2048_re1e4_energy.txt, written by make_long_rollout.py from the FP64
 # oracle: 2048^2 Taylor-Green, Re = 1e4, u0 = 0.05, uniform density, 20000
 # steps; energy of the 256^2 injection, total mass and eight node velocities
 # every 2000 steps.

@@ -1,11 +1,11 @@
 """The long high-Reynolds-number Taylor-Green rollout (2048^2, Re = 1e4,
 u0 = 0.05, 20000 steps; validation section's energy decay and "Reynolds
 Number Study") against the FP64 oracle's reference of the same flow, stored by
-tests/golden/make_cfg5.py: kinetic energy of the 256^2 injection and the
+tests/golden/make_long_rollout.py: kinetic energy of the 256^2 injection and the
 velocity at eight sampled nodes every 2000 steps, plus the total mass.
 
 Plain BGK through the library must reproduce the oracle within the FP32 bar
-(the spec velocity bar of 1e-5 relative after 1000 steps at u0 = 0.04,
+(the FP32 velocity bar of 1e-5 relative after 1000 steps at u0 = 0.04,
 scaled by steps / 1000 and 0.04 / u0: FP32 rounding enters the populations at
 a fixed fraction of their O(u0) size each step).  The corrected collision is
 a different method: for it the report's errors against the same reference are

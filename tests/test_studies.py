@@ -186,7 +186,7 @@ def test_sweep_trajectory_steps_match_the_oracle_near_tau_one_half(orc, trained,
 
     - The fallback decision agrees (BF16-emulating oracle, the kernel's
       storage precision).
-    - f* within the benchmark spec's 1e-3 of the FP64 oracle.
+    - f* within 1e-3 of the FP64 oracle (relative L2).
     - The correction delta* = f* - f*_BGK: at every node within 5e-2 of its
       largest value against the BF16-emulating oracle, and as a field within
       5e-2 of the FP64 oracle.  Near tau = 1/2 the correction is mostly
