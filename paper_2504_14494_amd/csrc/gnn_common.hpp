@@ -220,7 +220,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (in the caller's workspace): ctrl[0] = the step's decision, ctrl[1] =
 // workgroups of the producing kernel done, ctrl[2] = workgroups of the
 // fallback kernel done.  gnn_prep_kernel, which starts every step, zeroes
-// the two counts.  arrive == NULL means the step runs without the gate.
+// the two counts, and the tile counters of the message-passing rounds,
+// ctrl[kCtrlTileQueue + r].  arrive == NULL means the step runs without the
+// gate.
+constexpr int kCtrlTileQueue = 4;
+static_assert(kCtrlTileQueue + MAX_ROUNDS <= 64, "control words fit their 256 bytes");
 struct GateArgs {
   unsigned *ctrl;        // control words above, or NULL (no gate)
   double threshold;      // relative mass drift allowed per step
@@ -228,6 +232,53 @@ struct GateArgs {
   unsigned *n_fallback;  // steps that fell back, or NULL
   double *mass;          // total mass of the previous state (FP64), in/out
 };
+
+// Mass partials in exact fixed point: a signed 128-bit integer in units of
+// 2^-80 (hi * 2^64 + lo).  Integer addition is associative, so a total does
+// not depend on the order its terms are added in, which lets the last round
+// hand out tiles to whichever workgroup is free and still take the same gate
+// decision and record the same mass for the same state.  Each term is an
+// FP64 sum of a few FP32 populations; it is clamped to +-256 (a node whose
+// populations reach that has long failed the drift check; the clamp keeps
+// 2^27 terms far from overflow: 2^27 * 2^8 * 2^80 = 2^115) and truncated to
+// the grid (error below 2^-80 per term), NaN counting as 0 (the population
+// check flags it).
+struct Q80 {
+  unsigned long long lo;
+  long long hi;
+};
+
+__device__ __forceinline__ Q80 q80_add(Q80 a, Q80 b) {
+  Q80 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
+  return r;
+}
+
+__device__ __forceinline__ Q80 q80_of(double v) {
+  if (!(v == v)) v = 0.0;
+  v = fmin(fmax(v, -256.0), 256.0);
+  const double sc = v * 65536.0;  // exact: a power of two
+  const double h = floor(sc);
+  const double r = sc - h;        // exact, in [0, 1)
+  Q80 q;
+  q.hi = (long long)h;
+  q.lo = (unsigned long long)(r * 18446744073709551616.0);  // r * 2^64 < 2^64
+  return q;
+}
+
+// The value rounded to FP64 (the same integer always gives the same double).
+__device__ __forceinline__ double q80_value(Q80 q) {
+  return (double)q.hi * (1.0 / 65536.0) + (double)q.lo * 0x1p-80;
+}
+
+// Partial sums of either kind, added and read out in the gate below.
+__device__ __forceinline__ double part_add(double a, double b) { return a + b; }
+__device__ __forceinline__ Q80 part_add(Q80 a, Q80 b) { return q80_add(a, b); }
+__device__ __forceinline__ double part_value(double a) { return a; }
+__device__ __forceinline__ double part_value(Q80 a) { return q80_value(a); }
+template <typename P>
+__device__ __forceinline__ P part_zero() { return P{}; }
 
 // Called by all kThreads threads of every workgroup of the producing kernel,
 // after its thread 0 stored the workgroup's partials.  The workgroup that
@@ -238,9 +289,9 @@ struct GateArgs {
 // the fallback count, and the fallback kernel then writes the mass of what it
 // stored.  sm and sf are shared scratch of kThreads entries each; every
 // thread takes part in the barriers, so no thread may have left before.
-template <int kThreads>
-__device__ void gate_decide_last(const GateArgs &g, const double *pmass, const unsigned *pflag,
-                                 int nparts, double nodes, double *sm, unsigned *sf) {
+template <int kThreads, typename P>
+__device__ void gate_decide_last(const GateArgs &g, const P *pmass, const unsigned *pflag,
+                                 int nparts, double nodes, P *sm, unsigned *sf) {
   if (threadIdx.x == 0) {
     __threadfence();  // this workgroup's partials before its arrival
     const unsigned done = atomicAdd(&g.ctrl[1], 1u);
@@ -251,10 +302,10 @@ __device__ void gate_decide_last(const GateArgs &g, const double *pmass, const u
   __syncthreads();
   if (!last) return;
   __threadfence();  // every other workgroup's partials are visible
-  double m = 0.0;
+  P m = part_zero<P>();
   unsigned f = 0;
   for (int k = threadIdx.x; k < nparts; k += kThreads) {
-    m += pmass[k];
+    m = part_add(m, pmass[k]);
     f |= pflag[k];
   }
   sm[threadIdx.x] = m;
@@ -262,13 +313,13 @@ __device__ void gate_decide_last(const GateArgs &g, const double *pmass, const u
   __syncthreads();
   for (int s = kThreads / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
-      sm[threadIdx.x] += sm[threadIdx.x + s];
+      sm[threadIdx.x] = part_add(sm[threadIdx.x], sm[threadIdx.x + s]);
       sf[threadIdx.x] |= sf[threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double mnew = nodes + sm[0];
+    const double mnew = nodes + part_value(sm[0]);
     const double mold = *g.mass;
     unsigned fl = sf[0] ? 1u : 0u;
     const double rel = fabs(mnew - mold) / mold;

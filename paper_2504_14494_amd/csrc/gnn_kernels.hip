@@ -168,6 +168,8 @@ __global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ 
     ctrl[1] = 0u;
     ctrl[2] = 0u;
   }
+  // and so do the tile counters of the rounds
+  if (ctrl && f == 0 && lane < MAX_ROUNDS) ctrl[kCtrlTileQueue + lane] = 0u;
   if (f < F.nfrag) {
     const FragSrc fs = frag_src(L, F, R, f, lane & 15);
     long long ix[8];
@@ -399,7 +401,7 @@ constexpr int kHaloBytes = kStageLoads * 64 * 16;
 static_assert(kNodeBytes == 9 * 16, "a node is nine 16-byte slots");
 static_assert(kRowsPerWave * kRoundWaves == TILE_Y, "tile rows split over the waves");
 static_assert(TILE_X * TILE_Y * NOUT * 4 <= kHaloBytes, "head outputs fit in a halo buffer");
-static_assert(3 * kRoundThreads * 4 <= kHaloBytes, "reduction fits in a halo buffer");
+static_assert((16 + 4) * kRoundThreads <= kHaloBytes, "reduction fits in a halo buffer");
 // Divisions of the staging loop by multiply and shift (full-rate 24-bit
 // multiplies): slot / 9 for every slot of a halo buffer and node / HALO_X for
 // every node, checked here over the whole range.
@@ -424,6 +426,25 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 // tile included.  The loads into LDS are waited for explicitly
 // (kWaitVmcnt0) before the barrier that publishes them; the memory clobber
 // keeps the compiler from moving memory accesses across the barrier.
+// Stores a row's fragments (chunks q and 4 + q of the node in lane 16 q + n)
+// through a raw buffer resource of `bytes` bytes at `base`: stores at
+// offsets past the range are dropped by the hardware.
+constexpr int kNodeStateBytes = HID * 2;
+constexpr int kBufferRsrcWord3 = 0x00020000;
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_row(uint16_t *base, int bytes, int off, const u32x4 (&v)[2]) {
+  // base and bytes are wave-uniform; saying so keeps the resource in scalar
+  // registers (no per-lane loop over resources)
+  const uint64_t pb = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)pb);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pb >> 32));
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(((uint64_t)hi << 32) | lo), 0, __builtin_amdgcn_readfirstlane(bytes),
+      kBufferRsrcWord3);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4_t, v[0]), rs, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4_t, v[1]), rs, off + 64, 0, 0);
+}
+
 __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
@@ -432,7 +453,7 @@ template <bool HEAD, bool PULL, bool SAVE>
 __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
     const uint16_t *__restrict__ hin, uint16_t *__restrict__ hout,
     uint16_t *__restrict__ save_agg, int batch, int nx, int ny, int round,
-    const uint8_t *__restrict__ pack, FragLayout F, HeadArgs args) {
+    const uint8_t *__restrict__ pack, FragLayout F, HeadArgs args, unsigned *__restrict__ tileq) {
   __shared__ __attribute__((aligned(16))) uint8_t hs_a[kHaloBytes];
   __shared__ __attribute__((aligned(16))) uint8_t hs_b[kHaloBytes];
   __shared__ u32x4 wa_s[8 * 64];
@@ -471,8 +492,6 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
 
   const int txn = (nx + TILE_X - 1) / TILE_X, tyn = (ny + TILE_Y - 1) / TILE_Y;
   const long long ntiles = (long long)batch * txn * tyn;
-  double mass_acc = 0.0;
-  unsigned flag_acc = 0;
 
   struct TileAt {
     int x0, y0, b;
@@ -540,6 +559,25 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
     }
   };
 
+  Q80 mass_acc{0ull, 0ll};
+  unsigned flag_acc = 0;
+
+  // The last row's stores of the previous tile (without the head), issued
+  // once the barrier that starts a tile has passed.
+  bool pend = false;
+  size_t pend_row = 0;
+  int pend_bytes = 0, pend_off = 0;
+  u32x4 pend_hb[2] = {}, pend_ab[2] = {};
+  auto release = [&]() {
+    if constexpr (!HEAD) {
+      if (pend) {
+        if (hout) store_row(hout + pend_row * HID, pend_bytes, pend_off, pend_hb);
+        if constexpr (SAVE) store_row(save_agg + pend_row * HID, pend_bytes, pend_off, pend_ab);
+        pend = false;
+      }
+    }
+  };
+
   // The receivers of one tile from the halo in `hs`; with HEAD the head
   // outputs then pass through `hs` itself (float zb[TILE_X * TILE_Y][NOUT]).
   auto compute = [&](const TileAt &T, uint8_t *hs) {
@@ -562,76 +600,111 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       auto frag_at = [&](int dx, int dy, int s) {
         return *(const u32x4 *)(nb + ((dy + 1) * HALO_X + dx + 1) * kNodeBytes + s * 64);
       };
+      // Every LDS read of the row's receiver part is issued before the first
+      // wait: the receiver's state, the eight Wa fragments and the sender
+      // states of the first two edges.
       u32x4 hn[2] = {frag_at(0, 0, 0), frag_at(0, 0, 1)};
+      u32x4 waf[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) waf[k] = wa[k * 64];
+      // sender states of edge e in hj[e & 1], read one edge ahead of use
+      u32x4 hj[2][2];
+      hj[1][0] = frag_at(cx(1), cy(1), 0);
+      hj[1][1] = frag_at(cx(1), cy(1), 1);
+      hj[0][0] = frag_at(cx(2), cy(2), 0);
+      hj[0][1] = frag_at(cx(2), cy(2), 1);
       f32x4 an[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        an[t] = mfma(wa[(2 * t) * 64], hn[0], be[t]);
-        an[t] = mfma(wa[(2 * t + 1) * 64], hn[1], an[t]);
+        an[t] = mfma(waf[2 * t], hn[0], be[t]);
+        an[t] = mfma(waf[2 * t + 1], hn[1], an[t]);
       }
       f32x4 agg[4] = {};
       const uint32_t q0 = q == 0 ? 0xffffffffu : 0u;
       // Pre-activation of the message from direction d (MFMA only).
-      auto message = [&](int d, f32x4(&acc)[4]) {
-        const u32x4 hj[2] = {frag_at(cx(d), cy(d), 0), frag_at(cx(d), cy(d), 1)};
+      auto message = [&](int d, const u32x4(&h)[2], f32x4(&acc)[4]) {
         const u32x4 ed = {q0 & (bf16_unit(cx(d)) | (bf16_unit(cy(d)) << 16)), 0u, 0u, 0u};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           acc[t] = mfma(u32x4{wc[t], 0u, 0u, 0u}, ed, an[t]);
-          acc[t] = mfma(wb[t][0], hj[0], acc[t]);
-          acc[t] = mfma(wb[t][1], hj[1], acc[t]);
+          acc[t] = mfma(wb[t][0], h[0], acc[t]);
+          acc[t] = mfma(wb[t][1], h[1], acc[t]);
         }
       };
-      // Software pipeline over the 8 edges: the MFMA chains of edge d + 1 are
-      // issued before the GELUs of edge d, so the matrix cores work while the
-      // VALU evaluates the previous messages.  Summation order is unchanged.
+      // Software pipeline over the 8 edges: step d issues the LDS reads of
+      // edge d + 2, the MFMA chains of edge d + 1 and the GELUs of edge d,
+      // whose pre-activations were formed one step earlier.  A scheduling
+      // barrier closes each step, so the compiler cannot move a chain next to
+      // the GELUs that consume it (which would expose the MFMA latency);
+      // inside a step each of the 12 MFMAs is followed by 8 VALU
+      // instructions.  Summation order is unchanged.
       f32x4 acc[2][4];
-      message(1, acc[0]);
+      message(1, hj[1], acc[0]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int d = 1; d < 9; ++d) {
-        if (d < 8) message(d + 1, acc[d & 1]);
+        if (d + 2 <= 8) {
+          hj[d & 1][0] = frag_at(cx(d + 2), cy(d + 2), 0);
+          hj[d & 1][1] = frag_at(cx(d + 2), cy(d + 2), 1);
+        }
+        if (d < 8) message(d + 1, hj[(d + 1) & 1], acc[d & 1]);
 #pragma unroll
         for (int t = 0; t < 4; ++t) agg[t] += gelu4(acc[(d - 1) & 1][t]);
+        if (d + 2 <= 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
         if (d < 8) {
-          // issue order: the two LDS reads of edge d + 1, then each of its 12
-          // MFMAs followed by 8 of the VALU instructions of edge d's GELUs
 #pragma unroll
           for (int i = 0; i < 12; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
       u32x4 ab[2] = {frag_from_acc(agg[0], agg[1]), frag_from_acc(agg[2], agg[3])};
+      // Node update: the Wn fragments of row tile t + 1 are read while the
+      // chain of row tile t runs.
       f32x4 p[4];
+      u32x4 wnf[2][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wnf[0][k] = wn[k * 64];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        p[t] = mfma(wn[(4 * t) * 64], hn[0], bn[t]);
-        p[t] = mfma(wn[(4 * t + 1) * 64], hn[1], p[t]);
-        p[t] = mfma(wn[(4 * t + 2) * 64], ab[0], p[t]);
-        p[t] = mfma(wn[(4 * t + 3) * 64], ab[1], p[t]);
-        p[t] = gelu4(p[t]);
-      }
-      u32x4 hb[2] = {frag_from_acc(p[0], p[1]), frag_from_acc(p[2], p[3])};
-      // This wave's loads of the next tile's halo, issued at the start of the
-      // tile, are complete before its first store of the tile: the barrier
-      // that starts the next tile then needs no wait on memory, and the
-      // stores drain while the next tile is computed.  (The wait is in every
-      // row: before the second row it also covers the first row's stores,
-      // issued half a tile earlier; unconditional, it also tells the
-      // compiler that no load into a halo buffer is pending after a tile.)
-      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-      if (x < nx && y < ny) {
-        const size_t node = lat_nodes + (size_t)y * nx + x;
-        if (hout) {
-          u32x4 *dst = (u32x4 *)(hout + node * HID);
-          dst[q] = hb[0];
-          dst[4 + q] = hb[1];
+        if (t < 3) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) wnf[(t + 1) & 1][k] = wn[(4 * (t + 1) + k) * 64];
         }
-        if constexpr (SAVE) {
-          u32x4 *da = (u32x4 *)(save_agg + node * HID);
-          da[q] = ab[0];
-          da[4 + q] = ab[1];
+        const u32x4(&w)[4] = wnf[t & 1];
+        p[t] = mfma(w[0], hn[0], bn[t]);
+        p[t] = mfma(w[1], hn[1], p[t]);
+        p[t] = mfma(w[2], ab[0], p[t]);
+        p[t] = mfma(w[3], ab[1], p[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) p[t] = gelu4(p[t]);
+      u32x4 hb[2] = {frag_from_acc(p[0], p[1]), frag_from_acc(p[2], p[3])};
+      // The row's stores go through buffer resources whose range ends at
+      // the lattice edge (none for a row past it): the hardware drops the
+      // lanes outside the lattice.  Without the head, the last row's stores
+      // are held back until the barrier that starts the next tile has passed
+      // (see the wait below).
+      {
+        const int yu = __builtin_amdgcn_readfirstlane(y);
+        const bool row_in = yu < ny;
+        const size_t row0 = lat_nodes + (size_t)(row_in ? yu : ny - 1) * nx + x0;
+        const int bytes = row_in ? (nx - x0) * kNodeStateBytes : 0;
+        const int off = n * kNodeStateBytes + q * 16;
+        if (HEAD || r + 1 < kRowsPerWave) {
+          if (hout) store_row(hout + row0 * HID, bytes, off, hb);
+          if constexpr (SAVE) store_row(save_agg + row0 * HID, bytes, off, ab);
+        } else {
+          pend = true;
+          pend_row = row0;
+          pend_bytes = bytes;
+          pend_off = off;
+          pend_hb[0] = hb[0];
+          pend_hb[1] = hb[1];
+          pend_ab[0] = ab[0];
+          pend_ab[1] = ab[1];
         }
       }
       if constexpr (HEAD) {
@@ -640,7 +713,19 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       }
     }
 
+    // This wave's direct-to-LDS loads of the next tile's halo, issued before
+    // its rows, must be complete before the barrier that starts the next
+    // tile.  At this point only they, the stores released at the start of
+    // the tile and the first row's stores are in flight, all issued at least
+    // a row earlier, so the wait seldom stalls; the last row's stores, held
+    // back, drain while the next tile is computed.  A wait in every row,
+    // before its stores, cost a tenth of the round.
+    if constexpr (!HEAD) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+
     if constexpr (HEAD) {
+      // the halo loads are complete before the epilogue's own loads and
+      // stores are issued
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       // every wave is done reading the halo: its buffer takes the head outputs
       float *zb = (float *)hs;
       lds_barrier();
@@ -663,6 +748,8 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       const int x = x0 + nxl, y = y0 + tyl;
       const bool lo = (wave & 1) == 0;
       static_assert(TILE_X * TILE_Y == 2 * 64 && kRoundWaves == 4, "epilogue split");
+      double msum = 0.0;
+      unsigned bad = 0;
       if (x < nx && y < ny) {
         float z[NOUT];
 #pragma unroll
@@ -672,8 +759,6 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
         float gp[9];
         node_pops<PULL>(args.src + lat_off, nx, ny, x, y, gp);
         float *d = args.dst + lat_off + (size_t)y * 9 * nx + x;
-        double msum = 0.0;
-        unsigned bad = 0;
         auto finish = [&](int i) {
           __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
           float f = gp[i] + lbm::wgt<float>(i);
@@ -689,8 +774,6 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
 #pragma unroll
           for (int i = 5; i < 9; ++i) finish(i);
         }
-        mass_acc += msum;
-        flag_acc |= bad;
         const size_t node = lat_nodes + (size_t)y * nx + x;
         if (lo && args.head_out)
           for (int k = 0; k < NOUT; ++k) args.head_out[node * NOUT + k] = z[k];
@@ -698,6 +781,10 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
           if (lo)
             for (int k = 0; k < NOUT; ++k) args.save_z[node * 12 + k] = z[k];
       }
+      // Exact fixed-point accumulation: the gate's total does not depend on
+      // which workgroup drew which tile.
+      mass_acc = q80_add(mass_acc, q80_of(msum));
+      flag_acc |= bad;
     }
   };
 
@@ -708,44 +795,80 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
   // buffer (below for the first tile, inside the previous tile's work for the
   // others); the barrier at the top of each half makes all of them visible
   // and tells that the other buffer is no longer read.
+  //
+  // Tile order: the first two tiles of a workgroup are blockIdx.x and
+  // blockIdx.x + gridDim.x; every later one comes from a counter shared by
+  // the grid (zeroed by the weight packing each step), so that the two
+  // workgroups sharing a CU finish together even though the older one's
+  // waves are issued first (with a fixed assignment the younger one ran on
+  // alone for the last 40 % of the round).  Thread 0 draws the tile after
+  // next while the current one is computed and passes it on through `qslot`.
+  // Which workgroup computes a tile changes nothing in its results.
+  constexpr bool kQueue = true;
+  __shared__ long long qslot[2];
+  const long long g = gridDim.x;
+  unsigned drawn = 0;
+  auto draw = [&](long long nxt) {
+    if (kQueue && threadIdx.x == 0 && nxt < ntiles) {
+      // An address the compiler cannot prove wave-uniform: otherwise it
+      // rewrites the one-lane atomic into a wave-wide one and waits for its
+      // result at once, instead of where the result is used.
+      int z = 0;
+      asm volatile("" : "+v"(z));
+      drawn = atomicAdd(tileq + z, 1u);
+    }
+  };
+  auto after_next = [&](long long nxt) -> long long {
+    if (nxt >= ntiles) return ntiles;
+    return kQueue ? 2 * g + (long long)drawn : nxt + g;
+  };
   long long tile = blockIdx.x;
+  if (threadIdx.x == 0) qslot[1] = tile + g;
   if (tile < ntiles) stage(tile, hs_a);
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   while (tile < ntiles) {
     lds_barrier();
-    long long next = tile + gridDim.x;
+    long long next = qslot[1];
+    release();
     if (next < ntiles) stage(next, hs_b);
+    draw(next);
     compute(tile_at(tile), hs_a);
+    if (threadIdx.x == 0) qslot[0] = after_next(next);
     tile = next;
     if (tile >= ntiles) break;
     lds_barrier();
-    next = tile + gridDim.x;
+    next = qslot[0];
+    release();
     if (next < ntiles) stage(next, hs_a);
+    draw(next);
     compute(tile_at(tile), hs_b);
+    if (threadIdx.x == 0) qslot[1] = after_next(next);
     tile = next;
   }
+  release();
 
   if constexpr (HEAD) {
     __syncthreads();  // last tile's head outputs consumed
-    double *red_m = (double *)hs_a;
-    unsigned *red_f = (unsigned *)(hs_a + 8 * kRoundThreads);
+    Q80 *red_m = (Q80 *)hs_a;
+    unsigned *red_f = (unsigned *)(hs_a + sizeof(Q80) * kRoundThreads);
     red_m[threadIdx.x] = mass_acc;
     red_f[threadIdx.x] = flag_acc;
     __syncthreads();
     for (int s = kRoundThreads / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
-        red_m[threadIdx.x] += red_m[threadIdx.x + s];
+        red_m[threadIdx.x] = q80_add(red_m[threadIdx.x], red_m[threadIdx.x + s]);
         red_f[threadIdx.x] |= red_f[threadIdx.x + s];
       }
       __syncthreads();
     }
+    Q80 *pmass = (Q80 *)args.pmass;
     if (threadIdx.x == 0) {
-      args.pmass[blockIdx.x] = red_m[0];
+      pmass[blockIdx.x] = red_m[0];
       args.pflag[blockIdx.x] = red_f[0];
     }
     if constexpr (PULL) {
       if (args.gate.ctrl)
-        gate_decide_last<kRoundThreads>(args.gate, args.pmass, args.pflag, (int)gridDim.x,
+        gate_decide_last<kRoundThreads>(args.gate, pmass, args.pflag, (int)gridDim.x,
                                         (double)batch * nx * ny, red_m, red_f);
     }
   }
@@ -920,19 +1043,19 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
     if (!head) {
       if (save)
         hipLaunchKernelGGL((gnn_round_kernel<false, false, true>), dim3(rb), dim3(kRoundThreads), 0,
-                           s, hin, hout, sag, batch, nx, ny, r, pack, F, none);
+                           s, hin, hout, sag, batch, nx, ny, r, pack, F, none, ctrl + kCtrlTileQueue + r);
       else
         hipLaunchKernelGGL((gnn_round_kernel<false, false, false>), dim3(rb), dim3(kRoundThreads), 0,
-                           s, hin, hout, sag, batch, nx, ny, r, pack, F, none);
+                           s, hin, hout, sag, batch, nx, ny, r, pack, F, none, ctrl + kCtrlTileQueue + r);
     } else if (pull) {
       hipLaunchKernelGGL((gnn_round_kernel<true, true, false>), dim3(rb), dim3(kRoundThreads), 0, s,
-                         hin, hout, sag, batch, nx, ny, r, pack, F, ha);
+                         hin, hout, sag, batch, nx, ny, r, pack, F, ha, ctrl + kCtrlTileQueue + r);
     } else if (save) {
       hipLaunchKernelGGL((gnn_round_kernel<true, false, true>), dim3(rb), dim3(kRoundThreads), 0, s,
-                         hin, hout, sag, batch, nx, ny, r, pack, F, ha);
+                         hin, hout, sag, batch, nx, ny, r, pack, F, ha, ctrl + kCtrlTileQueue + r);
     } else {
       hipLaunchKernelGGL((gnn_round_kernel<true, false, false>), dim3(rb), dim3(kRoundThreads), 0, s,
-                         hin, hout, sag, batch, nx, ny, r, pack, F, ha);
+                         hin, hout, sag, batch, nx, ny, r, pack, F, ha, ctrl + kCtrlTileQueue + r);
     }
     if (int rc = launch_check("gnn_round_kernel")) return rc;
   }

@@ -82,8 +82,9 @@ constexpr int kMaxGnnBlocks = 2048;
 constexpr size_t kPackBytes = 512 * 1024;
 
 // Scratch of one forward pass: packed weights, two BF16 node-state buffers
-// (ping-pong), per-workgroup FP64 mass and flag partials of the corrected
-// collision and of the fallback step, and a few control words.
+// (ping-pong), per-workgroup mass and flag partials of the corrected
+// collision (fixed point, see gnn_common.hpp) and of the fallback step
+// (FP64), and a few control words.
 struct ForwardScratch {
   size_t pack, hA, hB, pmass, pflag, pmass2, ctrl, total;
 };
@@ -94,7 +95,7 @@ constexpr ForwardScratch forward_scratch(long long nodes) {
   F.pack = o; o += kPackBytes;
   F.hA = o; o += align256(n * HID * 2);
   F.hB = o; o += align256(n * HID * 2);
-  F.pmass = o; o += align256(kMaxGnnBlocks * sizeof(double));
+  F.pmass = o; o += align256(kMaxGnnBlocks * 16);  // 16-byte fixed-point partials
   F.pflag = o; o += align256(kMaxGnnBlocks * sizeof(unsigned));
   F.pmass2 = o; o += align256(kMaxGnnBlocks * sizeof(double));
   F.ctrl = o; o += 256;
