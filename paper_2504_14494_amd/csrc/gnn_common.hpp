@@ -207,6 +207,78 @@ struct ChunkWalk {
   }
 };
 
+// The chunks of ChunkWalk handed out dynamically, so that waves that are
+// issued first (the hardware favours the oldest workgroup of a CU) take more
+// chunks and all of them finish together; with a fixed share per wave the
+// last waves ran on alone for a third of the kernel.  The chunks are split
+// into kQueueParts contiguous parts, part p served by the workgroups
+// b = p (mod parts) (consecutive workgroups go to different XCDs, so each
+// part stays on one), each with its own counter: one counter for the whole
+// grid serialised the atomics.  A wave works through batches of kQueueBatch
+// consecutive chunks: its first batch by its index in the part, every later
+// one from the part's counter, drawn by lane 0 when the previous batch
+// starts, so the atomic's latency hides behind the batch.  Every member is
+// wave-uniform.  No result depends on which wave takes a chunk.
+constexpr int kQueueParts = 8;
+constexpr int kQueueBatch = 4;
+constexpr int kQueueStride = 32;  // words between two part counters (128 bytes)
+
+struct ChunkQueue {
+  int c, xc, y, b;  // current chunk, c >= nchunks when done
+  int cxn, ny, nchunks;
+  int base, len, cur, end, first_dyn;
+  unsigned *ctr;
+  unsigned drawn;   // lane 0's draw for the next batch
+  __device__ __forceinline__ ChunkQueue(int batch, int nx, int ny_, int waves_per_block,
+                                        int wave, unsigned *counters) {
+    const int w = __builtin_amdgcn_readfirstlane(wave);
+    cxn = (nx + 63) >> 6;
+    ny = ny_;
+    nchunks = batch * ny * cxn;
+    const int G = (int)gridDim.x, parts = G < kQueueParts ? G : kQueueParts;
+    const int p = (int)blockIdx.x % parts;
+    const int L = (nchunks + parts - 1) / parts;
+    base = p * L;
+    len = nchunks - base < L ? nchunks - base : L;
+    const int part_waves = ((G - 1 - p) / parts + 1) * waves_per_block;
+    first_dyn = part_waves * kQueueBatch;
+    ctr = counters + p * kQueueStride;
+    drawn = 0;
+    cur = ((int)blockIdx.x / parts * waves_per_block + w) * kQueueBatch;
+    begin_batch();
+  }
+  __device__ __forceinline__ void at(int local) {
+    c = base + local;
+    xc = c % cxn;
+    y = (c / cxn) % ny;
+    b = c / cxn / ny;
+  }
+  __device__ __forceinline__ void begin_batch() {
+    if (cur >= len) {
+      c = nchunks;
+      return;
+    }
+    end = cur + kQueueBatch < len ? cur + kQueueBatch : len;
+    at(cur);
+    if ((threadIdx.x & 63) == 0) {
+      // an address the compiler cannot prove wave-uniform: otherwise it makes
+      // the one-lane atomic wave-wide and waits for its result at once
+      int z = 0;
+      asm volatile("" : "+v"(z));
+      drawn = atomicAdd(ctr + z, (unsigned)kQueueBatch);
+    }
+  }
+  __device__ __forceinline__ bool more() const { return c < nchunks; }
+  __device__ __forceinline__ void next() {
+    if (++cur < end) {
+      at(cur);
+      return;
+    }
+    cur = first_dyn + (int)__builtin_amdgcn_readfirstlane(drawn);
+    begin_batch();
+  }
+};
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -220,11 +292,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (in the caller's workspace): ctrl[0] = the step's decision, ctrl[1] =
 // workgroups of the producing kernel done, ctrl[2] = workgroups of the
 // fallback kernel done.  gnn_prep_kernel, which starts every step, zeroes
-// the two counts, and the tile counters of the message-passing rounds,
-// ctrl[kCtrlTileQueue + r].  arrive == NULL means the step runs without the
+// the two counts, the tile counters of the message-passing rounds,
+// ctrl[kCtrlTileQueue + r], and the chunk counters of the encoder or of the
+// fused per-node step, ctrl[kCtrlChunkQueue + 32 p].  arrive == NULL means the step runs without the
 // gate.
 constexpr int kCtrlTileQueue = 4;
-static_assert(kCtrlTileQueue + MAX_ROUNDS <= 64, "control words fit their 256 bytes");
+constexpr int kCtrlChunkQueue = 32;  // kQueueParts counters, 128 bytes apart
+static_assert(kCtrlTileQueue + MAX_ROUNDS <= kCtrlChunkQueue, "control words");
+static_assert(kCtrlChunkQueue + kQueueParts * kQueueStride <= kCtrlWords, "control words fit their bytes");
 struct GateArgs {
   unsigned *ctrl;        // control words above, or NULL (no gate)
   double threshold;      // relative mass drift allowed per step
@@ -265,6 +340,25 @@ __device__ __forceinline__ Q80 q80_of(double v) {
   q.hi = (long long)h;
   q.lo = (unsigned long long)(r * 18446744073709551616.0);  // r * 2^64 < 2^64
   return q;
+}
+
+// Adds an FP32 value, rounded to the nearest multiple of 2^-40 (clamped
+// to +-256, as above), with full-rate FP32 and integer instructions only:
+// v 2^16 = h + r exactly (h integer, 0 <= r < 1), then r 2^24 is rounded to an
+// integer u, and the term is (h 2^24 + u) 2^-40 = (h 2^64 + u 2^40) 2^-80.
+__device__ __forceinline__ Q80 q80_add_f32(Q80 a, float v) {
+  v = __builtin_amdgcn_fmed3f(v, -256.0f, 256.0f);
+  const float sc = v * 65536.0f;                 // exact, |sc| <= 2^24
+  const float h = floorf(sc);
+  const float r = sc - h;                        // exact, in [0, 1)
+  const unsigned u = (unsigned)(r * 16777216.0f + 0.5f);  // <= 2^24 (2^24: a carry)
+  const int hi = (int)h + (int)(u >> 24);
+  // term = hi * 2^64 + (u mod 2^24) * 2^40 in 128 bits
+  const unsigned long long lo = (unsigned long long)(u & 0xFFFFFFu) << 40;
+  Q80 out;
+  out.lo = a.lo + lo;
+  out.hi = a.hi + (long long)hi + (out.lo < a.lo ? 1 : 0);
+  return out;
 }
 
 // The value rounded to FP64 (the same integer always gives the same double).

@@ -168,8 +168,9 @@ __global__ __launch_bounds__(64) void gnn_prep_kernel(const float *__restrict__ 
     ctrl[1] = 0u;
     ctrl[2] = 0u;
   }
-  // and so do the tile counters of the rounds
+  // and so do the tile counters of the rounds and the chunk counters
   if (ctrl && f == 0 && lane < MAX_ROUNDS) ctrl[kCtrlTileQueue + lane] = 0u;
+  if (ctrl && f == 0 && lane < kQueueParts) ctrl[kCtrlChunkQueue + kQueueStride * lane] = 0u;
   if (f < F.nfrag) {
     const FragSrc fs = frag_src(L, F, R, f, lane & 15);
     long long ix[8];
@@ -227,8 +228,8 @@ __device__ __forceinline__ void node_pops(const float *__restrict__ lat, int nx,
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-// One wave per chunk of 64 consecutive nodes of a lattice row, chunks taken
-// grid-stride with a wave-uniform walk.  Per node (one lane each): the
+// One wave per chunk of 64 consecutive nodes of a lattice row, chunks drawn
+// from a grid-wide counter (ChunkQueue).  Per node (one lane each): the
 // coalesced pull of the nine populations, the moments and the 12 normalised
 // features, rounded to BF16 into the node's LDS slot (16 BF16, the last four
 // zero).  The two layers then run on MFMA over four column blocks of 16 nodes,
@@ -239,7 +240,7 @@ template <bool PULL, bool SAVE>
 __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
     const float *__restrict__ g, int batch, int nx, int ny, const uint8_t *__restrict__ pack,
     FragLayout F, uint16_t *__restrict__ h0, uint16_t *__restrict__ save_x,
-    uint16_t *__restrict__ save_e1) {
+    uint16_t *__restrict__ save_e1, unsigned *__restrict__ chunkq) {
   __shared__ __attribute__((aligned(16))) uint32_t slot_s[kWaves][64 * 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, q = lane >> 4;
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
   }
   uint32_t *sw = slot_s[__builtin_amdgcn_readfirstlane(wave)];
 
-  for (ChunkWalk cw(batch, nx, ny, kWaves, wave); cw.more(); cw.next()) {
+  for (ChunkQueue cw(batch, nx, ny, kWaves, wave, chunkq); cw.more(); cw.next()) {
     const int xc = cw.xc, y = cw.y, b = cw.b;
     const float *lat = g + (size_t)b * ny * 9 * nx;
     {
@@ -943,6 +944,22 @@ using lbm::check_device;
 using lbm::fail;
 using lbm::launch_check;
 
+// Workgroups of the encoder resident per CU (every instance has the same
+// register budget; the occupancy query needs a current device).
+static int encode_blocks_per_cu() {
+  static int cached = 0;
+  if (cached == 0) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &v, reinterpret_cast<const void *>(&gnn_encode_kernel<true, false>), kThreads, 0) !=
+            hipSuccess ||
+        v <= 0)
+      v = 2;
+    cached = v;
+  }
+  return cached;
+}
+
 static int device_cus() {
   static int cached[64];
   int dev = 0;
@@ -1001,20 +1018,24 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
     return (uint16_t *)at(ws, (r & 1) ? W.hB : W.hA);
   };
 
+  // the encoder's grid: the workgroups that fit on the device at once (its
+  // registers allow three per CU); their waves draw the chunks from a counter,
+  // so a larger grid would only add workgroups that start late
   long long chunks = (long long)batch * ny * ((nx + 63) / 64);
   long long eblocks = (chunks + kWaves - 1) / kWaves;
-  int eb = (int)(eblocks < (long long)cus * 8 ? eblocks : (long long)cus * 8);
+  const long long eres = (long long)cus * encode_blocks_per_cu();
+  int eb = (int)(eblocks < eres ? eblocks : eres);
   uint16_t *sx = save ? (uint16_t *)at(saved, S.x) : nullptr;
   uint16_t *se = save ? (uint16_t *)at(saved, S.e1) : nullptr;
   if (pull) {
     hipLaunchKernelGGL((gnn_encode_kernel<true, false>), dim3(eb), dim3(kThreads), 0, s, src,
-                       batch, nx, ny, pack, F, hbuf(0), sx, se);
+                       batch, nx, ny, pack, F, hbuf(0), sx, se, ctrl + kCtrlChunkQueue);
   } else if (save) {
     hipLaunchKernelGGL((gnn_encode_kernel<false, true>), dim3(eb), dim3(kThreads), 0, s, src,
-                       batch, nx, ny, pack, F, hbuf(0), sx, se);
+                       batch, nx, ny, pack, F, hbuf(0), sx, se, ctrl + kCtrlChunkQueue);
   } else {
     hipLaunchKernelGGL((gnn_encode_kernel<false, false>), dim3(eb), dim3(kThreads), 0, s, src,
-                       batch, nx, ny, pack, F, hbuf(0), sx, se);
+                       batch, nx, ny, pack, F, hbuf(0), sx, se, ctrl + kCtrlChunkQueue);
   }
   if (int rc = launch_check("gnn_encode_kernel")) return rc;
 

@@ -77,6 +77,9 @@ inline size_t saved_bytes(int batch, int nx, int ny, int R) {
 // sizes the per-workgroup partial sums.
 constexpr int kMaxGnnBlocks = 2048;
 
+// Control words of a step (gate decision and arrival counts, work counters).
+constexpr int kCtrlWords = 512;
+
 // Bytes of the packed weight fragments (see gnn_common.hpp); generous bound
 // that holds for every n_rounds <= MAX_ROUNDS.
 constexpr size_t kPackBytes = 512 * 1024;
@@ -98,7 +101,7 @@ constexpr ForwardScratch forward_scratch(long long nodes) {
   F.pmass = o; o += align256(kMaxGnnBlocks * 16);  // 16-byte fixed-point partials
   F.pflag = o; o += align256(kMaxGnnBlocks * sizeof(unsigned));
   F.pmass2 = o; o += align256(kMaxGnnBlocks * sizeof(double));
-  F.ctrl = o; o += 256;
+  F.ctrl = o; o += kCtrlWords * 4;
   F.total = o;
   return F;
 }
@@ -118,10 +121,10 @@ inline SimpleScratch simple_scratch() {
   SimpleScratch S{};
   size_t o = 0;
   S.pack = o; o += kPackBytes;
-  S.pmass = o; o += align256(kMaxGnnBlocks * sizeof(double));
+  S.pmass = o; o += align256(kMaxGnnBlocks * 16);  // 16-byte fixed-point partials
   S.pflag = o; o += align256(kMaxGnnBlocks * sizeof(unsigned));
   S.pmass2 = o; o += align256(kMaxGnnBlocks * sizeof(double));
-  S.ctrl = o; o += 256;
+  S.ctrl = o; o += kCtrlWords * 4;
   S.total = o;
   return S;
 }

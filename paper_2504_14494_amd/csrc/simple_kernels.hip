@@ -100,7 +100,7 @@ __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], f
   }
 }
 
-// A wave takes 64 consecutive nodes of one lattice row, grid-stride, one
+// A wave takes 64 consecutive nodes of one lattice row (ChunkQueue), one
 // node per lane for everything that is per node: the coalesced pull of the
 // nine populations (kept in registers for the collision), the moments and the
 // 12 normalised features (rounded to BF16 into the node's LDS slot), and the
@@ -128,8 +128,8 @@ template <bool PULL, bool SAVE, bool WALLS>
 __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int batch, int nx, int ny,
     const float *__restrict__ tau_arr, float tau_s, float gx, const uint8_t *__restrict__ pack,
-    FragLayout F, float *__restrict__ head_out, double *__restrict__ pmass,
-    unsigned *__restrict__ pflag, SimpleSave sv, GateArgs gate) {
+    FragLayout F, float *__restrict__ head_out, Q80 *__restrict__ pmass,
+    unsigned *__restrict__ pflag, SimpleSave sv, GateArgs gate, unsigned *__restrict__ chunkq) {
   __shared__ u32x4 w_s[14 * 64];   // W1 (4), W2 (8), Wh (2) fragments
   __shared__ f32x4 b_s[9 * 4];     // b1 (4), b2 (4), bh (1), per channel group
   __shared__ __attribute__((aligned(16))) uint32_t slot_s[kWaves][64 * kSlot];
@@ -161,11 +161,11 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
   }
   __syncthreads();
   uint32_t *sw = slot_s[wave];
-  double mass_acc = 0.0;
+  Q80 mass_acc{0ull, 0ll};
   unsigned flag_acc = 0;
 
   const size_t row = (size_t)9 * nx;
-  for (ChunkWalk cw(batch, nx, ny, kWaves, wave); cw.more(); cw.next()) {
+  for (ChunkQueue cw(batch, nx, ny, kWaves, wave, chunkq); cw.more(); cw.next()) {
     const int xc = cw.xc, y = cw.y, b = cw.b;
     const float *lat = src + (size_t)b * ny * row;
     const int x = xc * 64 + lane;
@@ -263,7 +263,8 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
       collide<WALLS>(gp, z, tau, sdelta, gx, drho, rho, u, v);
       float *d = dst + (size_t)b * ny * row + (size_t)y * row + x;
       // node mass in FP32 (rounding ~1e-9 per node, ~1e-13 of the lattice
-      // mass), accumulated over the nodes in FP64.  A population is negative
+      // mass), accumulated over the nodes in exact fixed point (a total that
+      // does not depend on which wave took which chunk).  A population is negative
       // or not finite exactly when the smallest f_i is below zero or the sum
       // is not finite (an infinity or NaN anywhere reaches the sum; the
       // minimum skips NaN).
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
         msum += gp[i];
       }
       const unsigned bad = (fmin >= 0.0f && fabsf(msum) < INFINITY) ? 0u : 1u;
-      mass_acc += (double)msum;
+      mass_acc = q80_add_f32(mass_acc, msum);
       flag_acc |= bad;
       if (head_out) {
         const size_t node = ((size_t)b * ny + y) * nx + x;
@@ -292,14 +293,15 @@ __global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
 
   // every wave is done with its slots: the reduction reuses them
   __syncthreads();
-  double *red_m = (double *)&slot_s[0][0];
-  unsigned *red_f = &slot_s[0][0] + 2 * kThreads;
+  Q80 *red_m = (Q80 *)&slot_s[0][0];
+  unsigned *red_f = &slot_s[0][0] + 4 * kThreads;
+  static_assert(5 * kThreads <= kWaves * 64 * kSlot, "reduction fits in the slots");
   red_m[threadIdx.x] = mass_acc;
   red_f[threadIdx.x] = flag_acc;
   __syncthreads();
   for (int s = kThreads / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
-      red_m[threadIdx.x] += red_m[threadIdx.x + s];
+      red_m[threadIdx.x] = q80_add(red_m[threadIdx.x], red_m[threadIdx.x + s]);
       red_f[threadIdx.x] |= red_f[threadIdx.x + s];
     }
     __syncthreads();
@@ -352,11 +354,11 @@ static int launch_simple(bool pull, bool walls, float gx, const float *src, floa
   if (int rc = launch_prep(params, 0, pack, ctrl, s)) return rc;
   const long long chunks = (long long)batch * ny * ((nx + 63) / 64);
   long long blocks = (chunks + simple::kWaves - 1) / simple::kWaves;
-  // exactly the resident blocks: the grid-stride loop then ends evenly
+  // the resident blocks; their waves draw the chunks from a counter
   long long cap = (long long)simple_device_cus() * simple::kBlocksPerCu;
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   const int nb = (int)(blocks < cap ? blocks : cap);
-  double *pm = (double *)at_(ws, W.pmass);
+  Q80 *pm = (Q80 *)at_(ws, W.pmass);
   unsigned *pf = (unsigned *)at_(ws, W.pflag);
   GateArgs gate{};
   if (fb && pull) gate = GateArgs{ctrl, fb->drift_threshold, fb->flags, fb->n_fallback, fb->mass};
@@ -371,19 +373,19 @@ static int launch_simple(bool pull, bool walls, float gx, const float *src, floa
   if (pull && walls)
     hipLaunchKernelGGL((simple::simple_step_kernel<true, false, true>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, gx,
-                       pack, F, head_out, pm, pf, sv, gate);
+                       pack, F, head_out, pm, pf, sv, gate, ctrl + kCtrlChunkQueue);
   else if (pull)
     hipLaunchKernelGGL((simple::simple_step_kernel<true, false, false>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
-                       pack, F, head_out, pm, pf, sv, gate);
+                       pack, F, head_out, pm, pf, sv, gate, ctrl + kCtrlChunkQueue);
   else if (saved)
     hipLaunchKernelGGL((simple::simple_step_kernel<false, true, false>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
-                       pack, F, head_out, pm, pf, sv, gate);
+                       pack, F, head_out, pm, pf, sv, gate, ctrl + kCtrlChunkQueue);
   else
     hipLaunchKernelGGL((simple::simple_step_kernel<false, false, false>), dim3(nb),
                        dim3(simple::kThreads), 0, s, src, dst, batch, nx, ny, tau_arr, tau, 0.0f,
-                       pack, F, head_out, pm, pf, sv, gate);
+                       pack, F, head_out, pm, pf, sv, gate, ctrl + kCtrlChunkQueue);
   return launch_check("simple_step_kernel");
 }
 
