@@ -237,7 +237,7 @@ constexpr int kWaves = kThreads / 64;
 // group q < 2 takes features 8q..8q+7.  Lanes past the row end (ragged nx)
 // load a valid node and store nothing.
 template <bool PULL, bool SAVE>
-__global__ __launch_bounds__(kThreads) void gnn_encode_kernel(
+__global__ __launch_bounds__(kThreads, SAVE ? 3 : 4) void gnn_encode_kernel(
     const float *__restrict__ g, int batch, int nx, int ny, const uint8_t *__restrict__ pack,
     FragLayout F, uint16_t *__restrict__ h0, uint16_t *__restrict__ save_x,
     uint16_t *__restrict__ save_e1, unsigned *__restrict__ chunkq) {
@@ -727,6 +727,19 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       // the halo loads are complete before the epilogue's own loads and
       // stores are issued
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      // The collision of the tile's 128 nodes: waves 2j and 2j + 1 take nodes
+      // 64 j .. 64 j + 63, one per lane, and split the nine populations
+      // between them (0-4 and 5-8), so every lane of every wave works.  The
+      // populations are loaded first, so that their latency passes while the
+      // head outputs are exchanged (lanes past the lattice edge load a valid
+      // node and store nothing).
+      const int nl = (wave >> 1) * 64 + lane;
+      const int tyl = nl / TILE_X, nxl = nl - tyl * TILE_X;
+      const int x = x0 + nxl, y = y0 + tyl;
+      const bool inside = x < nx && y < ny;
+      const size_t lat_off = (size_t)b * ny * 9 * nx;
+      float gp[9];
+      node_pops<PULL>(args.src + lat_off, nx, ny, inside ? x : x0, inside ? y : y0, gp);
       // every wave is done reading the halo: its buffer takes the head outputs
       float *zb = (float *)hs;
       lds_barrier();
@@ -741,24 +754,15 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
         }
       }
       lds_barrier();
-      // The collision of the tile's 128 nodes: waves 2j and 2j + 1 take nodes
-      // 64 j .. 64 j + 63, one per lane, and split the nine populations
-      // between them (0-4 and 5-8), so every lane of every wave works.
-      const int nl = (wave >> 1) * 64 + lane;
-      const int tyl = nl / TILE_X, nxl = nl - tyl * TILE_X;
-      const int x = x0 + nxl, y = y0 + tyl;
       const bool lo = (wave & 1) == 0;
       static_assert(TILE_X * TILE_Y == 2 * 64 && kRoundWaves == 4, "epilogue split");
       double msum = 0.0;
       unsigned bad = 0;
-      if (x < nx && y < ny) {
+      if (inside) {
         float z[NOUT];
 #pragma unroll
         for (int k = 0; k < NOUT; ++k) z[k] = zb[nl * NOUT + k];
         const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
-        const size_t lat_off = (size_t)b * ny * 9 * nx;
-        float gp[9];
-        node_pops<PULL>(args.src + lat_off, nx, ny, x, y, gp);
         float *d = args.dst + lat_off + (size_t)y * 9 * nx + x;
         auto finish = [&](int i) {
           __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
@@ -1018,9 +1022,10 @@ int launch_forward(bool pull, const float *src, float *dst, int batch, int nx, i
     return (uint16_t *)at(ws, (r & 1) ? W.hB : W.hA);
   };
 
-  // the encoder's grid: the workgroups that fit on the device at once (its
-  // registers allow three per CU); their waves draw the chunks from a counter,
-  // so a larger grid would only add workgroups that start late
+  // the encoder's grid: the workgroups that fit on the device at once (four
+  // per CU for inference, three when saving activations); their waves draw
+  // the chunks from a counter, so a larger grid would only add workgroups
+  // that start late
   long long chunks = (long long)batch * ny * ((nx + 63) / 64);
   long long eblocks = (chunks + kWaves - 1) / kWaves;
   const long long eres = (long long)cus * encode_blocks_per_cu();
