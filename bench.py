@@ -162,6 +162,12 @@ def gnn_leg(n, steps, warmup):
 GNN_MAC_PER_NODE = 12 * 64 + 64 * 64 + 2 * (64 * 64 + 64 * 64 + 64 * 128) + 64 * 10
 GNN_GELU_PER_NODE = 128 + 2 * (8 * 64 + 64)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# One v_mfma_f32_16x16x32_bf16: 16 x 16 x 32 MAC, 16 cycles in the matrix
+# pipe, of which the SIMD's VALU issue loses about 4 (a GELU-bound probe with
+# the round kernel's chains of three dependent MFMAs: 12 MFMAs added 36-44
+# cycles to 16 GELUs' 641).
+MFMA_MAC_PER_INST = 16 * 16 * 32
+MFMA_ISSUE_CYCLES = 4.0
 # FP32 VALU without packed math: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
 # A GELU is 5 full-rate ops (x*x, fma, mul, add, mul) and 2 transcendentals
 # (v_exp_f32, v_rcp_f32) that each occupy the VALU for two issue slots
@@ -203,13 +209,15 @@ def gnn_roofline(ms_per_step, nodes, gelu_measured=None):
     if gelu_measured:
         alu["gelu_ceiling_measured"] = round(gelu_measured / 1e12, 3)
         alu["frac_of_measured"] = round(gelu_rate / gelu_measured, 4)
-    # The SIMD issues MFMA and VALU work of a wave one after the other (the
-    # counters of the round kernels add up to ~97 % busy), so the step's
-    # ceiling is the serialised issue time of its algorithmic work: per node
-    # 1,280 GELUs at 9 slots (16 lanes per cycle) plus the minimum MFMA work
-    # at 1,017 FLOP per SIMD cycle; peak 1024 SIMDs x 2.4 GHz.
+    # The VALU bounds the step: an MFMA runs in the matrix pipe while the
+    # SIMD issues VALU work (the round kernels' counters show VALU issue plus
+    # MFMA busy above 100 %), and costs the VALU only its own issue (about
+    # MFMA_ISSUE_CYCLES, measured).  The ceiling is therefore the issue time
+    # of the algorithmic work: per node 1,280 GELUs at 9 slots (16 lanes per
+    # cycle) plus the issue of the minimum MFMA work (38,272 MAC = 4.67
+    # 16x16x32 instructions); peak 1024 SIMDs x 2.4 GHz.
     simd_cycles = GNN_GELU_PER_NODE * GELU_SLOTS / 16.0 + \
-        2.0 * GNN_MAC_PER_NODE / (MFMA_BF16_PEAK_TFLOPS * 1e12 / (1024 * 2.4e9))
+        GNN_MAC_PER_NODE / MFMA_MAC_PER_INST * MFMA_ISSUE_CYCLES
     issue = simd_cycles * nodes / sec / 1e9
     r = {"roofline_mfma": {"bound": "mfma", "achieved": round(mfma_tf, 1),
                            "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -404,7 +412,7 @@ def simple_leg(n, steps, warmup, ms_bgk):
                               "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": round(mfma_tf / MFMA_BF16_PEAK_TFLOPS, 4)},
             "counters": None if t is None else {
-                k: t[k] for k in ("mfma_util", "valu_busy_tool", "valu_issue_est",
+                k: t[k] for k in ("mfma_util", "valu_issue_excl_mfma", "clock_ghz",
                                   "traffic_over_algorithmic")}}
 
 
