@@ -460,7 +460,10 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
   __shared__ u32x4 wa_s[8 * 64];
   __shared__ u32x4 wn_s[16 * 64];
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is wave-uniform; saying so keeps what derives from it (tile
+  // rows, the staging loop) in scalar registers
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int n = lane & 15, q = lane >> 4;
   const u32x4 *frags = (const u32x4 *)(pack + F.frag_off);
   const f32x4 *bias = (const f32x4 *)(pack + F.bias_off);
