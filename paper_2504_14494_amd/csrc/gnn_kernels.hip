@@ -398,6 +398,7 @@ constexpr int kRowsPerWave = TILE_Y / kRoundWaves;
 // (slot 9 ln + 8 is the padding of kNodeBytes); one direct-to-LDS load fills
 // 64 consecutive slots.
 constexpr int kStageLoads = (HNODES * 9 + 63) / 64;
+constexpr int kStagePerWave = (kStageLoads + kRoundWaves - 1) / kRoundWaves;
 constexpr int kHaloBytes = kStageLoads * 64 * 16;
 static_assert(kNodeBytes == 9 * 16, "a node is nine 16-byte slots");
 static_assert(kRowsPerWave * kRoundWaves == TILE_Y, "tile rows split over the waves");
@@ -513,34 +514,60 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
     return T;
   };
 
+  // Byte offset from the halo's first node of the 16 bytes that slot
+  // `slot` of a halo buffer takes in an interior tile: chunk c of halo node
+  // ln = (hx, hy), at (hy nx + hx) 128 + 16 c, with 24-bit multiplies
+  // (nx <= 2^20 keeps it in 32 bits; larger lattices take the general path).
+  const bool stage_interior_ok = nx <= (1 << 20);
+  auto stage_offset = [&](unsigned slot) -> unsigned {
+    unsigned ln = __umul24(slot, kDiv9Mul) >> 16;
+    unsigned c = slot - 9 * ln;
+    if (ln >= (unsigned)HNODES) {
+      ln = HNODES - 1;
+      c = 7;
+    }
+    c = c < 7 ? c : 7;
+    const unsigned hy = __umul24(ln, kDivHaloMul) >> 16;
+    const unsigned hx = ln - HALO_X * hy;
+    return (__umul24(hy, (unsigned)nx) + hx) * 128u + c * 16u;
+  };
+  // Without the head the kernel has the registers to compute this lane's
+  // offsets once (load k = wave + 4 i fills slot 64 k + lane, the same in
+  // every interior tile), which takes the address arithmetic out of the tile
+  // loop (-2 % of the round); the last round computes them per tile.
+  unsigned stage_off[kStagePerWave];
+#pragma unroll
+  for (int i = 0; i < kStagePerWave; ++i) {
+    const int k = wave + kRoundWaves * i;
+    stage_off[i] = HEAD ? 0u : stage_offset(64u * (k < kStageLoads ? k : 0) + lane);
+  }
+
   // Issues the direct-to-LDS loads of a tile's halo into `buf`: load k of
   // this wave fills slots 64 k .. 64 k + 63, lane l slot 64 k + l.  Padding
   // slots take a copy of chunk 7, slots past the last node a copy of the last
   // node: every address is a valid node state, every slot inside `buf`.
   auto stage = [&](long long tile, uint8_t *buf) {
     const TileAt T = tile_at(tile);
-    // Interior tiles (the halo wraps nowhere): node (hx, hy) of the halo is
-    // (hy * nx + hx) nodes past the halo's first node, a per-lane offset
-    // computed with 24-bit multiplies.  nx <= 2^20 keeps it in 32 bits.
+    // Interior tiles (the halo wraps nowhere): the loads take the offsets
+    // computed above from the halo's first node.
     if (T.x0 >= 1 && T.x0 + HALO_X - 1 <= nx && T.y0 >= 1 && T.y0 + HALO_Y - 1 <= ny &&
-        nx <= (1 << 20)) {
+        stage_interior_ok) {
       const uint8_t *base =
           (const uint8_t *)(hin + (T.lat_nodes + (size_t)(T.y0 - 1) * nx + (T.x0 - 1)) * HID);
-      for (int k = wave; k < kStageLoads; k += kRoundWaves) {
-        const unsigned slot = 64 * k + lane;
-        unsigned ln = __umul24(slot, kDiv9Mul) >> 16;
-        unsigned c = slot - 9 * ln;
-        if (ln >= (unsigned)HNODES) {
-          ln = HNODES - 1;
-          c = 7;
+      if constexpr (HEAD) {
+        for (int k = wave; k < kStageLoads; k += kRoundWaves)
+          __builtin_amdgcn_global_load_lds(
+              (const void *)(base + stage_offset(64u * k + lane)),
+              (__attribute__((address_space(3))) void *)(buf + k * 1024), 16, 0, 0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < kStagePerWave; ++i) {
+          const int k = wave + kRoundWaves * i;
+          if (k < kStageLoads)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(base + stage_off[i]),
+                (__attribute__((address_space(3))) void *)(buf + k * 1024), 16, 0, 0);
         }
-        c = c < 7 ? c : 7;
-        const unsigned hy = __umul24(ln, kDivHaloMul) >> 16;
-        const unsigned hx = ln - HALO_X * hy;
-        const unsigned off = (__umul24(hy, (unsigned)nx) + hx) * 128u + c * 16u;
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(base + off),
-            (__attribute__((address_space(3))) void *)(buf + k * 1024), 16, 0, 0);
       }
       return;
     }
