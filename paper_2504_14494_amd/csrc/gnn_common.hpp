@@ -167,47 +167,9 @@ __device__ __forceinline__ f32x4 load_bias(const f32x4 *__restrict__ bias, int b
 // Packs the FP32 blob into `pack` (frag_layout(R).total bytes) on stream s.
 int launch_prep(const float *params, int R, uint8_t *pack, unsigned *ctrl, hipStream_t s);
 
-// Makes the LDS writes of this wave visible to all of its lanes before the
-// reads that follow (LDS staging private to one wave).
-// Wave-uniform walk over chunks of 64 consecutive nodes of a lattice row:
-// chunk c = (b ny + y) cxn + xc over `batch` lattices of nx x ny, taken
-// grid-stride by the waves of the grid.  Every member is wave-uniform
-// (scalar registers): one division at the start, then a constant step with
-// carries.  batch nx ny < 2^31 keeps every index in int.
-struct ChunkWalk {
-  int c, xc, y, b;
-  int cxn, ny, nchunks, stride, step_x, step_y;
-  __device__ __forceinline__ ChunkWalk(int batch, int nx, int ny_, int waves_per_block,
-                                       int wave) {
-    const int w = __builtin_amdgcn_readfirstlane(wave);
-    cxn = (nx + 63) >> 6;
-    ny = ny_;
-    nchunks = batch * ny * cxn;
-    stride = (int)gridDim.x * waves_per_block;
-    step_x = stride % cxn;
-    step_y = stride / cxn;
-    c = (int)blockIdx.x * waves_per_block + w;
-    xc = c % cxn;
-    y = (c / cxn) % ny;
-    b = c / cxn / ny;
-  }
-  __device__ __forceinline__ bool more() const { return c < nchunks; }
-  __device__ __forceinline__ void next() {
-    c += stride;
-    xc += step_x;
-    y += step_y;
-    if (xc >= cxn) {
-      xc -= cxn;
-      ++y;
-    }
-    while (y >= ny) {
-      y -= ny;
-      ++b;
-    }
-  }
-};
-
-// The chunks of ChunkWalk handed out dynamically, so that waves that are
+// Chunks of 64 consecutive nodes of a lattice row, chunk c = (b ny + y) cxn
+// + xc over `batch` lattices of nx x ny (batch nx ny < 2^31 keeps every index
+// in int), handed out to the waves dynamically, so that waves that are
 // issued first (the hardware favours the oldest workgroup of a CU) take more
 // chunks and all of them finish together; with a fixed share per wave the
 // last waves ran on alone for a third of the kernel.  The chunks are split
@@ -279,6 +241,8 @@ struct ChunkQueue {
   }
 };
 
+// Makes the LDS writes of this wave visible to all of its lanes before the
+// reads that follow (LDS staging private to one wave).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

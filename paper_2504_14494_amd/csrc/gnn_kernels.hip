@@ -377,7 +377,7 @@ __device__ __forceinline__ void gnn_collide(float (&g)[9], const float (&z)[NOUT
   }
 }
 
-// One round over 16 x 8 receiver tiles taken grid-stride, two 4-wave
+// One round over 16 x 8 receiver tiles drawn from a counter, two 4-wave
 // workgroups per CU.  The node states of a tile and its ring (18 x 10 nodes,
 // BF16) sit in LDS; wave w handles tile rows 2w and 2w + 1, 16 receivers (one
 // MFMA column block) at a time.  Two halo buffers alternate: while the waves
