@@ -115,6 +115,7 @@ __device__ __forceinline__ void collide(float (&g)[9], const float (&z)[NOUT], f
 constexpr int kSlot = 12;   // dwords per node: 8 for the features, then 10 head outputs
 
 constexpr int kBlocksPerCu = 4;   // resident blocks (LDS 27 KB, <= 128 registers)
+constexpr int kBlocksPerCuSave = 3;   // the training forward, which also stores activations
 
 // What a training forward keeps per node for the backward pass: the BF16
 // operands the MFMAs consumed (features, both hidden layers, fragment order)
@@ -128,7 +129,7 @@ struct SimpleSave {
 // WALLS (with PULL): the channel step, halfway bounce-back at rows 0 and
 // ny - 1 and the body force rho * gx along x.
 template <bool PULL, bool SAVE, bool WALLS>
-__global__ __launch_bounds__(kThreads, kBlocksPerCu) void simple_step_kernel(
+__global__ __launch_bounds__(kThreads, SAVE ? kBlocksPerCuSave : kBlocksPerCu) void simple_step_kernel(
     const float *__restrict__ src, float *__restrict__ dst, int batch, int nx, int ny,
     const float *__restrict__ tau_arr, float tau_s, float gx, const uint8_t *__restrict__ pack,
     FragLayout F, float *__restrict__ head_out, Q80 *__restrict__ pmass,
@@ -392,7 +393,8 @@ static int launch_simple(bool pull, bool walls, float gx, const float *src, floa
   const long long chunks = (long long)batch * ny * ((nx + 63) / 64);
   long long blocks = (chunks + simple::kWaves - 1) / simple::kWaves;
   // the resident blocks; their waves draw the chunks from a counter
-  long long cap = (long long)simple_device_cus() * simple::kBlocksPerCu;
+  long long cap = (long long)simple_device_cus() *
+                  (saved && !pull ? simple::kBlocksPerCuSave : simple::kBlocksPerCu);
   if (cap > kMaxGnnBlocks) cap = kMaxGnnBlocks;
   const int nb = (int)(blocks < cap ? blocks : cap);
   Q80 *pm = (Q80 *)at_(ws, W.pmass);
