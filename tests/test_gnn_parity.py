@@ -343,6 +343,38 @@ def test_gate_mass_does_not_depend_on_the_work_order(net):
 
 # ------------------------------------------------------ full-size sample ---
 
+def test_ragged_lattice_with_counter_drawn_tiles_sampled_nodes(orc):
+    """A 1004 x 2008 lattice: the last tile column is half wide (2008 = 125 x
+    16 + 8) and the last tile row half high (1004 = 125 x 8 + 4), and with
+    15,876 tiles per round most are drawn from the counter.  300 random
+    nodes, every node of the corner tile and the four corners, against the
+    oracle evaluated on their own neighbourhoods."""
+    ny, nx = 1004, 2008
+    post = inputs.random_shifted_state((9, ny, nx), 3e-3, seed=47)
+    a = _dev(inputs.planes_to_rows(post))
+    b = torch.full_like(a, float("nan"))
+    blob = inputs.gnn_blob(13, R, s_delta=1e-4)
+    gnn.lbm_step_gnn(a, b, 0.7, _dev(blob), R)
+    torch.cuda.synchronize()
+    assert not torch.isnan(b).any().item()
+    fpre = orc.stream(post.astype(np.float64) + _w(orc))
+    rng = np.random.default_rng(1004)
+    corner = [(y, x) for y in range(1000, 1004) for x in range(2000, 2008)]
+    nodes = np.concatenate([rng.integers(0, nx * ny, 300),
+                            np.array([y * nx + x for y, x in corner]),
+                            np.array([0, nx - 1, nx * ny - 1, nx * (ny - 1)])])
+    ref, _ = orc.gnn_collide_nodes(fpre, 0.7, blob.astype(np.float64), nodes, R, mode=0)
+    ys, xs = nodes // nx, nodes % nx
+    got = b.double()[torch.as_tensor(ys), :, torch.as_tensor(xs)].cpu().numpy() + _w(orc)[:, 0, 0]
+    bgk = np.stack([orc.collide_bgk(fpre[:, y:y + 1, x:x + 1], 0.7)[:, 0, 0]
+                    for y, x in zip(ys, xs)])
+    rel = _rel(got, ref)
+    node_c = _node_max(got - bgk, ref - bgk)
+    print(f"1004 x 2008 sampled: f* rel-L2 {rel:.2e}, correction per node {node_c:.2e}")
+    assert rel <= 1e-3
+    assert node_c <= 5e-2
+
+
 def test_inference_workload_2048_sampled_nodes(orc):
     """The 2048^2 inference workload in the benchmark's launch configuration:
     100 BGK steps of Taylor-Green (Re = 1000, u0 = 0.04), then one corrected

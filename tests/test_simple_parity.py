@@ -159,3 +159,27 @@ def test_full_size_8192_sampled_rows(orc):
         got = dst[y].double().cpu().numpy() + w[:, :, 0]
         assert _rel(got, ref) <= 1e-3, y
         assert _node_max(got - bgk, ref - bgk) <= 5e-2, y
+
+
+def test_ragged_lattice_with_dynamically_drawn_chunks(orc):
+    """A 1004 x 2008 lattice: each row ends in a partial chunk (2008 = 31 x 64
+    + 24), and with 32,128 chunks the waves draw most of them from the
+    counters after their first batch.  Five whole rows, including both wrap
+    rows, against the oracle."""
+    ny, nx = 1004, 2008
+    blob = _blob(5, 1e-4)
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    src = torch.randn((ny, 9, nx), device="cuda", generator=gen) * 3e-3
+    dst = torch.full_like(src, float("nan"))
+    gnn.lbm_step_simple(src, dst, 0.7, _dev(blob))
+    assert not torch.isnan(dst).any().item()
+    w = _w(orc)
+    for y in (0, 1, 501, 1002, 1003):
+        rows = [(y - 1) % ny, y, (y + 1) % ny]
+        band = inputs.rows_to_planes(src[rows].double().cpu().numpy()) + w
+        fpre = orc.stream(band)
+        ref = orc.gnn_collide(fpre, 0.7, blob.astype(np.float64), 0, mode=0, act=1)[:, 1, :]
+        bgk = orc.collide_bgk(fpre, 0.7)[:, 1, :]
+        got = dst[y].double().cpu().numpy() + w[:, :, 0]
+        assert _rel(got, ref) <= 1e-3, y
+        assert _node_max(got - bgk, ref - bgk) <= 5e-2, y
