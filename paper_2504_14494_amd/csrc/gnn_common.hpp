@@ -178,8 +178,8 @@ int launch_prep(const float *params, int R, uint8_t *pack, unsigned *ctrl, hipSt
 // part stays on one), each with its own counter: one counter for the whole
 // grid serialised the atomics.  A wave works through batches of kQueueBatch
 // consecutive chunks: its first batch by its index in the part, every later
-// one from the part's counter, drawn by lane 0 when the previous batch
-// starts, so the atomic's latency hides behind the batch.  Every member is
+// one from the part's counter, drawn by lane 0 in the first chunk of the
+// previous batch, so the atomic's latency hides behind that chunk's loads.  Every member is
 // wave-uniform.  No result depends on which wave takes a chunk.
 constexpr int kQueueParts = 8;
 constexpr int kQueueBatch = 4;
@@ -190,7 +190,8 @@ struct ChunkQueue {
   int cxn, ny, nchunks;
   int base, len, cur, end, first_dyn;
   unsigned *ctr;
-  unsigned drawn;   // lane 0's draw for the next batch
+  int nxt;     // first chunk (in the part) of the next batch, once taken
+  bool fresh;  // the current chunk starts its batch: its draw is to be issued and taken
   __device__ __forceinline__ ChunkQueue(int batch, int nx, int ny_, int waves_per_block,
                                         int wave, unsigned *counters) {
     const int w = __builtin_amdgcn_readfirstlane(wave);
@@ -205,7 +206,7 @@ struct ChunkQueue {
     const int part_waves = ((G - 1 - p) / parts + 1) * waves_per_block;
     first_dyn = part_waves * kQueueBatch;
     ctr = counters + p * kQueueStride;
-    drawn = 0;
+    nxt = len;
     cur = ((int)blockIdx.x / parts * waves_per_block + w) * kQueueBatch;
     begin_batch();
   }
@@ -222,12 +223,29 @@ struct ChunkQueue {
     }
     end = cur + kQueueBatch < len ? cur + kQueueBatch : len;
     at(cur);
-    if ((threadIdx.x & 63) == 0) {
+    fresh = true;
+  }
+  // In the first chunk of a batch, lane 0 draws the next batch: draw() before
+  // the chunk's loads, take() once they have been waited for (which waited for
+  // the draw too).  The draw passes from one to the other in a register local
+  // to the chunk, so no register still waiting for the atomic is carried
+  // around the loop: such a register is copied at the loop's end, and the copy
+  // waited for every memory operation, the chunk's fresh stores included.
+  __device__ __forceinline__ unsigned draw() const {
+    unsigned d = 0;
+    if (fresh && (threadIdx.x & 63) == 0) {
       // an address the compiler cannot prove wave-uniform: otherwise it makes
       // the one-lane atomic wave-wide and waits for its result at once
       int z = 0;
       asm volatile("" : "+v"(z));
-      drawn = atomicAdd(ctr + z, (unsigned)kQueueBatch);
+      d = atomicAdd(ctr + z, (unsigned)kQueueBatch);
+    }
+    return d;
+  }
+  __device__ __forceinline__ void take(unsigned d) {
+    if (fresh) {
+      nxt = first_dyn + (int)__builtin_amdgcn_readfirstlane(d);
+      fresh = false;
     }
   }
   __device__ __forceinline__ bool more() const { return c < nchunks; }
@@ -236,7 +254,7 @@ struct ChunkQueue {
       at(cur);
       return;
     }
-    cur = first_dyn + (int)__builtin_amdgcn_readfirstlane(drawn);
+    cur = nxt;
     begin_batch();
   }
 };

@@ -270,10 +270,12 @@ __global__ __launch_bounds__(kThreads, SAVE ? 3 : 4) void gnn_encode_kernel(
     const float *lat = g + (size_t)b * ny * 9 * nx;
     {
       const int x = xc * 64 + lane;
+      const unsigned drawn = cw.draw();
       float gp[9];
       node_pops<PULL>(lat, nx, ny, x < nx ? x : nx - 1, y, gp);
       float drho, rho, u, v, uu;
       lbm::node_moments(gp, drho, rho, u, v, uu);
+      cw.take(drawn);
       const float raw[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
                                 gp[6], gp[7], gp[8], drho, u,     v};
       float ft[NFEAT];
@@ -548,6 +550,13 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
   // node: every address is a valid node state, every slot inside `buf`.
   auto stage = [&](long long tile, uint8_t *buf) {
     const TileAt T = tile_at(tile);
+    // With the head, the lane index is recounted here (mbcnt) rather than
+    // kept: held across the tile it was spilled to scratch, and reloading it
+    // made every tile wait for all of the previous tile's stores.
+    int sl = lane;
+    if constexpr (HEAD) {
+      asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(sl));
+    }
     // Interior tiles (the halo wraps nowhere): the loads take the offsets
     // computed above from the halo's first node.
     if (T.x0 >= 1 && T.x0 + HALO_X - 1 <= nx && T.y0 >= 1 && T.y0 + HALO_Y - 1 <= ny &&
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       if constexpr (HEAD) {
         for (int k = wave; k < kStageLoads; k += kRoundWaves)
           __builtin_amdgcn_global_load_lds(
-              (const void *)(base + stage_offset(64u * k + lane)),
+              (const void *)(base + stage_offset(64u * k + sl)),
               (__attribute__((address_space(3))) void *)(buf + k * 1024), 16, 0, 0);
       } else {
 #pragma unroll
@@ -572,7 +581,7 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       return;
     }
     for (int k = wave; k < kStageLoads; k += kRoundWaves) {
-      const int slot = 64 * k + lane;
+      const int slot = 64 * k + sl;
       int ln = slot / 9;
       int c = slot - 9 * ln;
       if (ln >= HNODES) ln = HNODES - 1;
@@ -614,7 +623,11 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
   auto compute = [&](const TileAt &T, uint8_t *hs) {
     const int x0 = T.x0, y0 = T.y0, b = T.b;
     const size_t lat_nodes = T.lat_nodes;
-    f32x4 zr[kRowsPerWave];
+    // head outputs of the wave's two rows: row 0's in zr0, row 1's in zr1
+    // (shifted along row by row; an array indexed by the row counter costs
+    // a select per element and position)
+    static_assert(kRowsPerWave == 2, "head outputs of two rows per wave");
+    f32x4 zr0 = {}, zr1 = {};
 #pragma unroll 1
     for (int r = 0; r < kRowsPerWave; ++r) {
       // An offset the compiler cannot see through, so that the LDS weight
@@ -740,7 +753,8 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       }
       if constexpr (HEAD) {
         f32x4 z = mfma(wh[0], hb[0], bh);
-        zr[r] = mfma(wh[1], hb[1], z);
+        zr0 = zr1;
+        zr1 = mfma(wh[1], hb[1], z);
       }
     }
 
@@ -776,7 +790,8 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
 #pragma unroll
       for (int r = 0; r < kRowsPerWave; ++r) {
         const int tyl = wave * kRowsPerWave + r;
-        const float zz[4] = {zr[r].x, zr[r].y, zr[r].z, zr[r].w};
+        const f32x4 zv = r == 0 ? zr0 : zr1;
+        const float zz[4] = {zv.x, zv.y, zv.z, zv.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           int k = 4 * q + e;
@@ -788,11 +803,21 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
       static_assert(TILE_X * TILE_Y == 2 * 64 && kRoundWaves == 4, "epilogue split");
       double msum = 0.0;
       unsigned bad = 0;
-      if (inside) {
-        float z[NOUT];
+      // Every lane collides (lanes past the edge hold a valid node), so the
+      // loaded populations are consumed on every path; only the stores depend
+      // on `inside`.  With the collision inside the branch, the compiler saw a
+      // path on which the loads were still in flight at the next tile and
+      // waited for all memory operations at the first row of every other
+      // tile, the next tile's halo loads included.
+      float z[NOUT];
 #pragma unroll
-        for (int k = 0; k < NOUT; ++k) z[k] = zb[nl * NOUT + k];
-        const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
+      for (int k = 0; k < NOUT; ++k) z[k] = zb[nl * NOUT + k];
+      const float tau = args.tau_arr ? args.tau_arr[b] : args.tau;
+      if (lo)
+        gnn_collide<0, 5>(gp, z, tau, sdelta);
+      else
+        gnn_collide<5, 9>(gp, z, tau, sdelta);
+      if (inside) {
         float *d = args.dst + lat_off + (size_t)y * 9 * nx + x;
         auto finish = [&](int i) {
           __builtin_nontemporal_store(gp[i], d + (size_t)i * nx);
@@ -801,11 +826,9 @@ __global__ __launch_bounds__(kRoundThreads, 2) void gnn_round_kernel(
           msum += (double)gp[i];
         };
         if (lo) {
-          gnn_collide<0, 5>(gp, z, tau, sdelta);
 #pragma unroll
           for (int i = 0; i < 5; ++i) finish(i);
         } else {
-          gnn_collide<5, 9>(gp, z, tau, sdelta);
 #pragma unroll
           for (int i = 5; i < 9; ++i) finish(i);
         }

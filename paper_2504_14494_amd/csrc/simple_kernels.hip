@@ -174,6 +174,7 @@ __global__ __launch_bounds__(kThreads, SAVE ? kBlocksPerCuSave : kBlocksPerCu) v
     const float *lat = src + (size_t)b * ny * row;
     const int x = xc * 64 + lane;
     const bool valid = x < nx;
+    const unsigned drawn = cw.draw();
     float gp[9];
     float drho, rho, u, v;  // kept for the collision
     {
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(kThreads, SAVE ? kBlocksPerCuSave : kBlocksPerCu) v
     }
     {
       moments(gp, drho, rho, u, v);
+      cw.take(drawn);
       const float uf = WALLS ? u + 0.5f * gx : u;  // Guo's velocity on the channel
       const float raw[NFEAT] = {gp[0], gp[1], gp[2], gp[3], gp[4], gp[5],
                                 gp[6], gp[7], gp[8], drho, uf,    v};
