@@ -343,13 +343,16 @@ def test_gate_mass_does_not_depend_on_the_work_order(net):
 
 # ------------------------------------------------------ full-size sample ---
 
-def test_ragged_lattice_with_counter_drawn_tiles_sampled_nodes(orc):
-    """A 1004 x 2008 lattice: the last tile column is half wide (2008 = 125 x
-    16 + 8) and the last tile row half high (1004 = 125 x 8 + 4), and with
-    15,876 tiles per round most are drawn from the counter.  300 random
-    nodes, every node of the corner tile and the four corners, against the
-    oracle evaluated on their own neighbourhoods."""
-    ny, nx = 1004, 2008
+@pytest.mark.parametrize("ny,nx", [(1004, 2008), (1001, 1950)])
+def test_ragged_lattice_with_counter_drawn_tiles_sampled_nodes(orc, ny, nx):
+    """Ragged lattices whose work is mostly drawn from the counters.
+    1004 x 2008: the last tile column is half wide (2008 = 125 x 16 + 8), the
+    last tile row half high (1004 = 125 x 8 + 4), 15,876 tiles per round.
+    1001 x 1950: the last tile row is one node high and the last column 14
+    wide; the encoder's 31 chunks per row make 31,031 chunks, whose eight
+    parts (3,879 and 3,878 chunks) each end in a batch of fewer than four.
+    300 random nodes, every node of the corner tile and the four corners,
+    against the oracle evaluated on their own neighbourhoods."""
     post = inputs.random_shifted_state((9, ny, nx), 3e-3, seed=47)
     a = _dev(inputs.planes_to_rows(post))
     b = torch.full_like(a, float("nan"))
@@ -358,8 +361,9 @@ def test_ragged_lattice_with_counter_drawn_tiles_sampled_nodes(orc):
     torch.cuda.synchronize()
     assert not torch.isnan(b).any().item()
     fpre = orc.stream(post.astype(np.float64) + _w(orc))
-    rng = np.random.default_rng(1004)
-    corner = [(y, x) for y in range(1000, 1004) for x in range(2000, 2008)]
+    rng = np.random.default_rng(ny)
+    ty0, tx0 = ny - (ny % 8 or 8), nx - (nx % 16 or 16)
+    corner = [(y, x) for y in range(ty0, ny) for x in range(tx0, nx)]
     nodes = np.concatenate([rng.integers(0, nx * ny, 300),
                             np.array([y * nx + x for y, x in corner]),
                             np.array([0, nx - 1, nx * ny - 1, nx * (ny - 1)])])
@@ -370,7 +374,7 @@ def test_ragged_lattice_with_counter_drawn_tiles_sampled_nodes(orc):
                     for y, x in zip(ys, xs)])
     rel = _rel(got, ref)
     node_c = _node_max(got - bgk, ref - bgk)
-    print(f"1004 x 2008 sampled: f* rel-L2 {rel:.2e}, correction per node {node_c:.2e}")
+    print(f"{ny} x {nx} sampled: f* rel-L2 {rel:.2e}, correction per node {node_c:.2e}")
     assert rel <= 1e-3
     assert node_c <= 5e-2
 

@@ -161,12 +161,13 @@ def test_full_size_8192_sampled_rows(orc):
         assert _node_max(got - bgk, ref - bgk) <= 5e-2, y
 
 
-def test_ragged_lattice_with_dynamically_drawn_chunks(orc):
-    """A 1004 x 2008 lattice: each row ends in a partial chunk (2008 = 31 x 64
-    + 24), and with 32,128 chunks the waves draw most of them from the
-    counters after their first batch.  Five whole rows, including both wrap
-    rows, against the oracle."""
-    ny, nx = 1004, 2008
+@pytest.mark.parametrize("ny,nx", [(1004, 2008), (1001, 1950)])
+def test_ragged_lattice_with_dynamically_drawn_chunks(orc, ny, nx):
+    """Ragged lattices whose chunks the waves mostly draw from the counters
+    after their first batch.  1004 x 2008: each row ends in a partial chunk
+    (2008 = 31 x 64 + 24), 32,128 chunks.  1001 x 1950: 31,031 chunks, whose
+    eight parts (3,879 and 3,878 chunks) each end in a batch of fewer than
+    four.  Five whole rows, including both wrap rows, against the oracle."""
     blob = _blob(5, 1e-4)
     gen = torch.Generator(device="cuda").manual_seed(9)
     src = torch.randn((ny, 9, nx), device="cuda", generator=gen) * 3e-3
@@ -174,7 +175,7 @@ def test_ragged_lattice_with_dynamically_drawn_chunks(orc):
     gnn.lbm_step_simple(src, dst, 0.7, _dev(blob))
     assert not torch.isnan(dst).any().item()
     w = _w(orc)
-    for y in (0, 1, 501, 1002, 1003):
+    for y in (0, 1, ny // 2, ny - 2, ny - 1):
         rows = [(y - 1) % ny, y, (y + 1) % ny]
         band = inputs.rows_to_planes(src[rows].double().cpu().numpy()) + w
         fpre = orc.stream(band)
