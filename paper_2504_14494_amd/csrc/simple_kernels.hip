@@ -197,6 +197,11 @@ __global__ __launch_bounds__(kThreads, SAVE ? kBlocksPerCuSave : kBlocksPerCu) v
               gp[i] = r1[(size_t)lbm::opp(i) * nx + xv];
             else
               gp[i] = r[(size_t)i * nx + xsrc];
+          } else if (cx(i) == 0) {
+            // no other chunk reads these lines (the shifted directions share
+            // their edge lines with the neighbouring chunks): non-temporal,
+            // -0.5 % (all nine non-temporal: +1.3 %)
+            gp[i] = __builtin_nontemporal_load(r + (size_t)i * nx + xsrc);
           } else {
             gp[i] = r[(size_t)i * nx + xsrc];
           }
