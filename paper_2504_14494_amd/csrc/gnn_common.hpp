@@ -179,8 +179,9 @@ int launch_prep(const float *params, int R, uint8_t *pack, unsigned *ctrl, hipSt
 // grid serialised the atomics.  A wave works through batches of kQueueBatch
 // consecutive chunks: its first batch by its index in the part, every later
 // one from the part's counter, drawn by lane 0 in the first chunk of the
-// previous batch, so the atomic's latency hides behind that chunk's loads.  Every member is
-// wave-uniform.  No result depends on which wave takes a chunk.
+// previous batch, so the atomic's latency hides behind that chunk's loads.
+// Every member is wave-uniform.  No result depends on which wave takes a
+// chunk.
 constexpr int kQueueParts = 8;
 constexpr int kQueueBatch = 4;
 constexpr int kQueueStride = 32;  // words between two part counters (128 bytes)
